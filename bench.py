@@ -1,0 +1,251 @@
+"""Benchmark: laminography forward + adjoint pairs per second on one MI355X.
+
+One step = one pair lam_fwd (u -> d, F*_2D F_u2D F_u1D) + lam_adj
+(d -> u, F*_u1D F*_u2D F_2D) on complex64 device arrays, inputs resident in
+HBM before timing starts.  Workload (default): 512^3 volume, 512 angles
+uniform in [0, 2 pi), tilt 30 deg, 512 x 512 detector, R = 2, m = 4; u is the
+seeded blob + cube phantom, d seeded complex N(0,1).
+
+Prints one JSON line.  Besides the contract fields it reports:
+  roofline       dominant kernel's algorithmic rate against its bound,
+                 from per-kernel HIP events in a second pass of the same steps
+  pair_hbm_frac  the whole pair's algorithmic bytes (u, u1, u2, d traffic) / time / 8 TB/s
+  fp64_*         the same kernels instantiated in complex128 (the plain FP64 operator)
+  accuracy       c64 vs c128 GPU (whole arrays) and c64 vs the FP64 oracle on sampled slices
+  cpu_baseline   the FP64 oracle timed on a bounded sample on this host
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VALU_TFLOPS = 78.6        # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
+TFLOPS_FP64 = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n0, n1, n2, ntheta, h, w, s, su):
+    """Bytes one operator must move (u read, u1 written + read, u2 written + read, d written)."""
+    V, H1, P = n0 * n1 * n2, h * n1 * n2, ntheta * h * w
+    return su * V + 2 * s * H1 + 3 * s * P
+
+
+def kernel_units(name, plan, s, su, slab):
+    """Algorithmic bytes per launch and taps per launch for each kernel.
+
+    Per unit (one column of F_u1D, one k_v slice of F_u2D, one projection of
+    the 2D DFT) the kernel's share of the operator's algorithmic traffic:
+    zfwd / zadj: s_u*V + s*H1 for the volume; F_u2D kernels: s*(n1 n2 + ntheta w)
+    per slice; rowfft / colfft: 2 s P per pass."""
+    n0, n1, n2, nt, h, w = plan.n0, plan.n1, plan.n2, plan.ntheta, plan.h, plan.w
+    if name in ("zfwd", "zadj"):
+        return su * n0 * n1 * n2 + s * h * n1 * n2
+    if name in ("rowfft", "colfft"):
+        return 2 * s * nt * h * w
+    return s * (n1 * n2 + nt * w) * slab
+
+
+def time_pairs(plan, u, d, steps, warmup):
+    import torch
+
+    out_d = torch.empty_like(d)
+    out_u = torch.empty_like(u)
+    for _ in range(warmup):
+        plan.fwd(u, out=out_d)
+        plan.adj(d, out=out_u)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        plan.fwd(u, out=out_d)
+        plan.adj(d, out=out_u)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return e0.elapsed_time(e1) / steps, wall, out_d, out_u
+
+
+def cpu_baseline(wl, budget_slices=4):
+    """Time the FP64 oracle on a bounded sample of one pair and scale to pairs/s.
+
+    Sample: F_u1D / F*_u1D on 1/64 of the (y, x) columns, F_u2D / F*_u2D on
+    `budget_slices` k_v slices, F*_2D / F_2D on 8 projections; each part is
+    scaled by (total units / sampled units)."""
+    import numpy as np
+
+    from oracle import lam_oracle as O
+
+    n, nt, h = wl["n"], wl["ntheta"], wl["det"]
+    g = O.Geometry(n, n, n, nt, math.radians(wl["phi_deg"]), h, h, 2, 4)
+    rng = np.random.default_rng(0)
+
+    def cplx(*shape):
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+    ncol = n * n // 64
+    _, _, nu_z = O.frequencies(g)
+    x = cplx(n, ncol)
+    t = time.perf_counter(); f = O.usfft1d_fwd(x, n * nu_z, 2, 4); t_z = time.perf_counter() - t
+    t = time.perf_counter(); O.usfft1d_adj(f, n * nu_z, n, 2, 4); t_za = time.perf_counter() - t
+    sl = list(range(h // 2 - budget_slices // 2, h // 2 + budget_slices // 2))
+    u1 = np.zeros((h, n, n), complex)
+    for k in sl:
+        u1[k] = cplx(n, n)
+    t = time.perf_counter(); r = O.fu2d(u1, g, kv_list=sl); t_2 = time.perf_counter() - t
+    t = time.perf_counter(); O.fu2d_adj(r, g, kv_list=sl); t_2a = time.perf_counter() - t
+    p8 = cplx(8, h, h)
+    t = time.perf_counter(); O.f2d_inv(p8); t_f = time.perf_counter() - t
+    t = time.perf_counter(); O.f2d(p8); t_fa = time.perf_counter() - t
+    per_pair = ((t_z + t_za) * 64 + (t_2 + t_2a) * h / len(sl) + (t_f + t_fa) * nt / 8)
+    sample_s = t_z + t_za + t_2 + t_2a + t_f + t_fa
+    return {
+        "value": 1.0 / per_pair,
+        "unit": "pairs/s",
+        "cores": O.WORKERS,
+        "kind": "oracle",
+        "sample": (f"F_u1D+adj on {ncol} of {n * n} columns, F_u2D+adj on {len(sl)} of {h} slices, "
+                   f"F*_2D+F_2D on 8 of {nt} projections; {sample_s:.1f} s of CPU time, scaled"),
+        "seconds_per_pair": per_pair,
+    }
+
+
+def sampled_oracle_check(plan, u_host, kv_list):
+    """c64 GPU L^ u vs the FP64 oracle on a few k_v slices (full F_u1D on the host)."""
+    import numpy as np
+    import torch
+
+    from oracle import lam_oracle as O
+
+    g = O.Geometry(plan.n0, plan.n1, plan.n2, plan.ntheta, plan.phi, plan.h, plan.w, 2, plan.m)
+    u1 = O.fu1d(u_host, g)
+    ref = O.fu2d(u1, g, kv_list=kv_list)[:, kv_list, :]
+    got = plan.fwd_hat(torch.from_numpy(u_host).to(plan.dtype).cuda())[:, kv_list, :].cpu().numpy()
+    return O.relerr(got.astype(np.complex128), ref)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lam512")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle accuracy check")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2511_01893_amd import inputs as I
+    from paper_2511_01893_amd import lam
+
+    wl = I.WORKLOADS[args.workload]
+    n, nt, h = wl["n"], wl["ntheta"], wl["det"]
+    phi = math.radians(wl["phi_deg"])
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {args.workload}: n={n} ntheta={nt} det={h} phi={wl['phi_deg']} c64")
+
+    plan = lam.Plan(n, ntheta=nt, phi=phi, h=h, w=h, dtype=torch.complex64, device=dev)
+    blobs = I.draw_blobs(wl["seed"], wl["nblobs"], cube_layer=wl["cubes"], n=n)
+    u = I.blob_phantom_torch((n, n, n), blobs, dev, torch.float32).to(torch.complex64)
+    d = I.random_complex_torch((nt, h, h), wl["seed"] + 200, dev, torch.complex64)
+    torch.cuda.synchronize()
+
+    ms, wall_ms, d64, u64 = time_pairs(plan, u, d, args.steps, args.warmup)
+    log(f"[bench] c64 pair {ms:.3f} ms (host wall {wall_ms:.3f} ms)")
+    B_pair = 2 * algorithmic_bytes(n, n, n, nt, h, h, 8, 8)
+
+    # per-kernel durations: second pass of the same steps with events around every kernel
+    plan.profile(True)
+    for _ in range(args.steps):
+        plan.fwd(u)
+        plan.adj(d)
+    prof = plan.profile_read()
+    plan.profile(False)
+    kern = {}
+    for name, (tot, cnt) in prof.items():
+        if cnt:
+            kern[name] = {"ms_total_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
+                          "avg_launch_ms": tot / cnt}
+    dom = max(kern, key=lambda k: kern[k]["ms_total_per_step"])
+    log("[bench] kernels: " + ", ".join(f"{k} {v['ms_total_per_step']:.3f} ms/step x{v['launches_per_step']:.0f}"
+                                        for k, v in kern.items()))
+    # slab of this plan = h / launches of gather per op
+    plan_slab = int(round(h / kern["gather"]["launches_per_step"])) if "gather" in kern else h
+    bytes_launch = kernel_units(dom, plan, 8, 8, plan_slab)
+    ach = bytes_launch / (kern[dom]["avg_launch_ms"] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bytes_launch,
+            "avg_launch_ms": kern[dom]["avg_launch_ms"]}
+
+    result = {
+        "metric": "lam fwd+adj pairs/s at 512^3 (c64 vs FP64, rel err <=1e-4); % HBM roofline",
+        "value": 1000.0 / ms,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n}^3 volume, {nt} angles, tilt {wl['phi_deg']:g} deg, "
+                               f"{h}x{h} detector, R=2, m=4, blob phantom seed {wl['seed']}",
+                   "n": n, "ntheta": nt, "det": h, "phi_deg": wl["phi_deg"], "oversample": 2, "m": 4,
+                   "slab": plan_slab},
+        "pair_algorithmic_bytes": B_pair,
+        "pair_hbm_frac": B_pair / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "roofline": roof,
+        "kernels": kern,
+    }
+
+    if not args.no_fp64:
+        plan128 = lam.Plan(n, ntheta=nt, phi=phi, h=h, w=h, dtype=torch.complex128, device=dev)
+        u128, d128 = u.to(torch.complex128), d.to(torch.complex128)
+        ms128, _, dd, uu = time_pairs(plan128, u128, d128, max(3, args.steps // 2), 1)
+        result["fp64_ms_per_step"] = ms128
+        result["fp64_pairs_per_s"] = 1000.0 / ms128
+        result["speedup_vs_fp64"] = ms128 / ms
+        e_f = ((d64.to(torch.complex128) - dd).norm() / dd.norm()).item()
+        e_a = ((u64.to(torch.complex128) - uu).norm() / uu.norm()).item()
+        result["accuracy"] = {"c64_vs_c128_fwd": e_f, "c64_vs_c128_adj": e_a}
+        log(f"[bench] c128 pair {ms128:.3f} ms; c64 vs c128 fwd {e_f:.2e} adj {e_a:.2e}")
+        del plan128, u128, d128, dd, uu
+        torch.cuda.empty_cache()
+
+    if not args.no_check:
+        t = time.perf_counter()
+        kvs = [h // 2 - h // 4, h // 2 + 3]
+        err = sampled_oracle_check(plan, u.real.double().cpu().numpy().astype(np.complex128), kvs)
+        result.setdefault("accuracy", {})["c64_vs_oracle_fwd_hat_sampled"] = err
+        result["accuracy"]["oracle_sample"] = f"L^ u on k_v slices {kvs} (all angles, all k_u)"
+        log(f"[bench] c64 vs oracle (slices {kvs}) {err:.2e} in {time.perf_counter() - t:.1f} s")
+
+    if not args.no_cpu:
+        t = time.perf_counter()
+        result["cpu_baseline"] = cpu_baseline(wl)
+        log(f"[bench] cpu baseline {result['cpu_baseline']['value']:.3e} pairs/s in {time.perf_counter() - t:.1f} s")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

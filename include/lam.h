@@ -1,0 +1,187 @@
+/*
+ * lam.h - C ABI of the MI355X laminography operator library (liblam.so).
+ *
+ * The library computes the forward laminography operator of ADMM-FFT
+ * laminography, L = F*_2D F_u2D F_u1D, and its adjoint
+ * L* = F*_u1D F*_u2D F_2D (Section 2, Algorithm 1, forward and adjoint
+ * passes), the frequency-domain pair L^ = F_u2D F_u1D / L^* used after the
+ * cancellation F_2D F*_2D = I (Section 4.2, Algorithm 2), with the data
+ * subtraction fused into F_u2D, and one ADMM-TV iteration built on them
+ * (Section 2, Equation 1 and Algorithm 2).
+ *
+ * Conventions (the paper gives the factorisation and array shapes; the
+ * geometry and the unequally-spaced FFT follow the Fourier-slice theorem
+ * and Gaussian gridding, Dutt & Rokhlin 1993 / Greengard & Lee 2004):
+ *   - u: volume (n0, n1, n2) = (z, y, x), C order, z = rotation axis.  The
+ *     paper writes u[n1, n0, n2]; this is the same array with the rotation
+ *     axis stored slowest.  Centred indices j in [-n/2, n/2).
+ *   - d: projections (ntheta, h, w) = (angle, detector row v, column p).
+ *   - theta_t = 2 pi t / ntheta unless an explicit angle list is given.
+ *   - Frequency of detector bin (k_v, k_u):
+ *       nu = (k_u/w) (cos t, sin t, 0) + (k_v/h) (sin phi sin t, -sin phi cos t, cos phi)
+ *     as (x, y, z), cycles per voxel; forward exponent exp(-2 pi i nu.j).
+ *   - F*_2D is the centred inverse DFT with 1/(h w); the adjoint's F_2D is
+ *     the centred forward DFT with 1/(h w).  L^ carries no normalisation, so
+ *     L = W^H L^ / (h w) with W the unnormalised centred 2D DFT.
+ *   - USFFT: oversampling R, half-width m (2m taps per axis), M = R n,
+ *     tau = pi m / (n^2 R (R - 1/2)), beta = pi (R - 1/2)/(R m),
+ *     deconvolution c(j) = sqrt(pi/tau) exp(tau j^2) / M.
+ *
+ * Memory.  Every array argument is a DEVICE pointer to a contiguous C-order
+ * buffer owned by the caller.  Complex arrays are interleaved (re, im):
+ * float pairs for LAM_C64, double pairs for LAM_C128.  Real arrays (the
+ * *_real entry points and the ADMM state) are float for LAM_C64 and double
+ * for LAM_C128.  The library never allocates device memory: scratch space is
+ * the caller's workspace (lam_workspace_bytes / lam_set_workspace).
+ *
+ * Execution.  Every compute call only enqueues kernels on the given HIP
+ * stream (a hipStream_t passed as void*, NULL = default stream) and returns;
+ * no call synchronises the host.  One call at a time per plan: calls on one
+ * plan share its workspace, so calls that overlap in time (different
+ * streams, different threads) race.
+ *
+ * Errors.  Every call returns a lam_status.  Argument errors are reported
+ * before anything is enqueued and leave all outputs untouched.  LAM_ERR_HIP
+ * means a HIP runtime call failed (no device, launch failure); asynchronous
+ * device faults surface at a later call or stream synchronisation.
+ * lam_last_error() gives a thread-local text for the last failing call.
+ * NaN or Inf inputs are not checked: they propagate to the outputs.
+ */
+#ifndef LAM_H
+#define LAM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lam_plan_s* lam_plan;
+
+typedef enum { LAM_C64 = 0, LAM_C128 = 1 } lam_dtype;
+
+typedef enum {
+  LAM_OK = 0,
+  LAM_ERR_ARG = 1,        /* invalid argument or unsupported size           */
+  LAM_ERR_NOMEM = 2,      /* host allocation failed                          */
+  LAM_ERR_HIP = 3,        /* a HIP runtime call failed                       */
+  LAM_ERR_WORKSPACE = 4,  /* no workspace set, or the one given is too small */
+  LAM_ERR_STATE = 5       /* call not valid in the plan's current state      */
+} lam_status;
+
+/* Problem statement (Section 2: volume n0 x n1 x n2, ntheta projection
+ * angles, detector h x w; plus tilt, oversampling and kernel half-width). */
+typedef struct {
+  int n0, n1, n2;        /* volume (z, y, x); powers of two, 16 .. 4096            */
+  int ntheta;            /* number of projection angles, >= 1                       */
+  const double* theta;   /* host array [ntheta] in radians, or NULL: 2 pi t/ntheta  */
+  double phi;            /* tilt of the rotation axis from the tomographic
+                            position, radians, 0 <= phi < pi/2 (phi = 0: tomography) */
+  int h, w;              /* detector rows (k_v) and columns (k_u); powers of two,
+                            16 .. 4096                                              */
+  int oversample;        /* R; must be 2                                            */
+  int m;                 /* Gaussian half-width, 1 .. 8 (2m taps per axis)          */
+  lam_dtype dtype;       /* LAM_C64: complex64 data, FP32 accumulation, FP64
+                            coordinates/weights; LAM_C128: complex128 throughout    */
+  int slab;              /* k_v slices per internal slab of the 2D step; 0 = auto.
+                            Bounds the oversampled-grid scratch to slab slices.     */
+} lam_params;
+
+/* Validate the parameters and build the plan's FP64 tables on the host
+ * (angles, deconvolution factors, z-gather bases and weights, twiddles).
+ * Touches no device.  *out receives the plan; lam_destroy releases it.
+ * Errors: LAM_ERR_ARG (null pointers, sizes outside the ranges above, R != 2,
+ * m outside 1..8, phi outside [0, pi/2), theta non-finite), LAM_ERR_NOMEM. */
+int lam_init(lam_plan* out, const lam_params* p);
+
+/* Bytes of device workspace the plan needs (tables + stage buffers). */
+size_t lam_workspace_bytes(lam_plan p);
+
+/* Hand the plan a device workspace of at least lam_workspace_bytes(p) bytes
+ * (256-byte aligned), owned by the caller for the plan's lifetime, and copy
+ * the plan's tables into it (a synchronous host-to-device copy).  Must be
+ * called once before any compute call; calling it again moves the plan to
+ * the new workspace.  Errors: LAM_ERR_ARG (null/misaligned pointer),
+ * LAM_ERR_WORKSPACE (too small), LAM_ERR_HIP (copy failed or no device). */
+int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes);
+
+/* d = L u: forward laminography operator (Algorithm 1, forward pass).
+ * u: complex (n0, n1, n2); d: complex (ntheta, h, w).  u and d must not
+ * overlap.  d is also used as scratch for F_u2D's output. */
+int lam_fwd(lam_plan p, const void* u, void* d, void* hip_stream);
+
+/* u = L* d: adjoint (Algorithm 1, adjoint pass).  d: complex (ntheta, h, w),
+ * read only; u: complex (n0, n1, n2). */
+int lam_adj(lam_plan p, const void* d, void* u, void* hip_stream);
+
+/* As lam_fwd / lam_adj with a real volume u (float or double per dtype):
+ * d = L u for real u, and u = Re(L* d). */
+int lam_fwd_real(lam_plan p, const void* u, void* d, void* hip_stream);
+int lam_adj_real(lam_plan p, const void* d, void* u, void* hip_stream);
+
+/* r = L^ u - dhat (Algorithm 2 forward pass; the subtraction is fused into
+ * F_u2D's gather, Section 4.2 "Operation Cancellation and Fusion").
+ * u: complex volume; dhat: complex (ntheta, h, w) or NULL (then r = L^ u);
+ * r: complex (ntheta, h, w).  r may alias dhat. */
+int lam_fwd_hat(lam_plan p, const void* u, const void* dhat, void* r, void* hip_stream);
+
+/* u = L^* r, the exact adjoint of lam_fwd_hat's linear part (no 1/(h w)).
+ * r: complex (ntheta, h, w), read only; u: complex volume. */
+int lam_adj_hat(lam_plan p, const void* r, void* u, void* hip_stream);
+
+/* ADMM-TV state for lam_admm_step: all device pointers, caller-owned, real
+ * arrays of the plan's real type (float for LAM_C64, double for LAM_C128).
+ *   u      [n0 n1 n2]        reconstruction (updated)
+ *   psi    [3][n0 n1 n2]     auxiliary variable psi ~ grad u (updated)
+ *   lam    [3][n0 n1 n2]     multiplier lambda (updated)
+ *   work   lam_admm_work_bytes(p) bytes of device scratch
+ *   scal   device array of 8 doubles: scal[0] = rho (updated), scal[1] = alpha,
+ *          scal[2..7] are written with diagnostics (last CG step, primal and
+ *          dual residuals).  FP64 throughout. */
+typedef struct {
+  void* u;
+  void* psi;
+  void* lam;
+  void* work;
+  double* scal;
+} lam_admm_state;
+
+/* Bytes of ADMM scratch lam_admm_step needs beyond the plan workspace. */
+size_t lam_admm_work_bytes(lam_plan p);
+
+/* One ADMM-TV iteration for min_u 1/2 |L u - d|^2 + alpha |u|_TV (Equation 1):
+ * LSP by n_inner conjugate-gradient steps in the cancelled frequency domain
+ * (Algorithm 2: one L^ and one L^* per step, the subtraction of dhat fused,
+ * Fletcher-Reeves directions, exact line search, FP64 scalars kept on the
+ * device), then the TV subproblem (isotropic shrink), the multiplier update
+ * and residual-balanced penalty update.  dhat = W d, complex (ntheta, h, w).
+ * Enqueues work only; no host synchronisation. */
+int lam_admm_step(lam_plan p, const lam_admm_state* s, const void* dhat, int n_inner, void* hip_stream);
+
+/* Per-kernel timing, for measurement.  With profiling on, every kernel the
+ * plan launches is bracketed by a pair of HIP events recorded on its stream
+ * (this adds a small gap between kernels).  lam_profile_read waits for the
+ * recorded events, returns per-kernel totals in milliseconds and launch
+ * counts in arrays of LAM_NUM_KERNELS entries indexed as lam_kernel_name
+ * lists them, and clears the record.  Kernels: 0 zfwd (F_u1D), 1 ycol_fwd,
+ * 2 xrow_fwd, 3 gather (F_u2D), 4 rowfft, 5 colfft (F*_2D / F_2D),
+ * 6 scatter, 7 xrow_adj, 8 ycol_adj (F*_u2D), 9 zadj (F*_u1D). */
+#define LAM_NUM_KERNELS 10
+int lam_profile(lam_plan p, int on);
+int lam_profile_read(lam_plan p, double* total_ms, long long* launches);
+const char* lam_kernel_name(int k);
+
+/* Release the plan (host memory only; the workspace stays the caller's). */
+void lam_destroy(lam_plan p);
+
+/* Static text for a status code. */
+const char* lam_error_string(int code);
+
+/* Thread-local detail text for the last failing call ("" if none). */
+const char* lam_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAM_H */

@@ -1,0 +1,467 @@
+// Host plan and C ABI of liblam.so (declared in include/lam.h).
+//
+// lam_init validates the problem statement and builds every table in FP64
+// on the host; lam_set_workspace copies them into the caller's device
+// workspace; the compute entry points only enqueue kernels on the caller's
+// stream.  The 2D step runs over slabs of k_v slices so that the
+// oversampled grids never need more than `slab` slices of scratch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lam.h"
+#include "lam_internal.hpp"
+#include "lam_admm.hpp"
+
+using namespace lam;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+bool is_pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+int ilog2(long v) { int r = 0; while ((1L << r) < v) ++r; return r; }
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+constexpr size_t kLdsMax = 160 * 1024;
+constexpr int kVPT = 16;
+
+}  // namespace
+
+struct lam_plan_s {
+  lam_params p{};
+  std::vector<double> theta;
+  int M0 = 0, M1 = 0, M2 = 0, Ntw = 0, slab = 0;
+  double beta = 0;
+  size_t csize = 8, rsize = 4;
+  // host tables (FP64)
+  std::vector<double> tw, cz, cy, cx, zw, cth, sth, rc;
+  std::vector<int> zbase;
+  // workspace layout (byte offsets)
+  size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zw = 0, off_cth = 0, off_sth = 0,
+         off_rc = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Dims D{};
+  LaunchCfg cfg{};
+  // optional per-kernel timing (lam_profile)
+  bool prof_on = false;
+  struct Rec { int slot; hipEvent_t a, b; };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Rec> recs;
+  ~lam_plan_s() {
+    for (auto& r : recs) { ev_pool.push_back(r.a); ev_pool.push_back(r.b); }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+std::vector<double> deconv(int n, int R, int m) {
+  const double M = (double)R * n;
+  const double tau = M_PI * m / ((double)n * n * R * (R - 0.5));
+  std::vector<double> c(n);
+  for (int a = 0; a < n; ++a) {
+    const double j = a - n / 2;
+    c[a] = std::sqrt(M_PI / tau) * std::exp(tau * j * j) / M;
+  }
+  return c;
+}
+
+void col_cfg(int log2N, int ncols, size_t csize, int& log2TX, int& threads, size_t& lds) {
+  const long N = 1L << log2N;
+  int TX = 16;
+  while (TX > 1 && (TX > ncols || N * TX * (long)csize > 131072 || N * TX / kVPT > 1024)) TX >>= 1;
+  log2TX = ilog2(TX);
+  threads = (int)std::max<long>(64, N * TX / kVPT);
+  lds = (size_t)N * TX * csize;
+}
+
+void row_cfg(int log2N, long nrows, size_t csize, int& log2RB, int& threads, size_t& lds) {
+  const long N = 1L << log2N;
+  int RB = 16;
+  while (RB > 1 && (RB > nrows || N * RB * (long)csize > 131072 || N * RB / kVPT > 1024 || nrows % RB)) RB >>= 1;
+  log2RB = ilog2(RB);
+  threads = (int)std::max<long>(64, N * RB / kVPT);
+  lds = (size_t)N * RB * csize;
+}
+
+int build(lam_plan_s* P) {
+  const lam_params& p = P->p;
+  const int R = p.oversample, m = p.m;
+  P->csize = p.dtype == LAM_C64 ? 8 : 16;
+  P->rsize = P->csize / 2;
+  P->M0 = R * p.n0; P->M1 = R * p.n1; P->M2 = R * p.n2;
+  P->beta = M_PI * (R - 0.5) / (R * (double)m);
+  P->Ntw = std::max({P->M0, P->M1, P->M2, p.h, p.w});
+  // twiddles exp(-2 pi i t / Ntw) in FP64
+  P->tw.resize(2 * (size_t)P->Ntw);
+  for (int t = 0; t < P->Ntw; ++t) {
+    const double a = 2.0 * M_PI * (double)t / (double)P->Ntw;
+    P->tw[2 * t] = std::cos(a);
+    P->tw[2 * t + 1] = -std::sin(a);
+  }
+  P->cz = deconv(p.n0, R, m);
+  P->cy = deconv(p.n1, R, m);
+  P->cx = deconv(p.n2, R, m);
+  // z-gather: targets xi_z = n0 (k_v / h) cos(phi), s = R xi_z
+  P->zbase.resize(p.h);
+  P->zw.resize((size_t)p.h * 2 * m);
+  for (int av = 0; av < p.h; ++av) {
+    const double kv = (double)(av - p.h / 2) / (double)p.h;
+    const double s = R * (p.n0 * (kv * std::cos(p.phi)));
+    const double b = std::floor(s), d = s - b;
+    P->zbase[av] = (int)b;
+    for (int i = 0; i < 2 * m; ++i) {
+      const double o = (double)(i - m + 1);
+      P->zw[(size_t)av * 2 * m + i] = std::exp(-P->beta * (d - o) * (d - o));
+    }
+  }
+  P->cth.resize(p.ntheta);
+  P->sth.resize(p.ntheta);
+  for (int t = 0; t < p.ntheta; ++t) {
+    P->cth[t] = std::cos(P->theta[t]);
+    P->sth[t] = std::sin(P->theta[t]);
+  }
+  P->rc.assign(16, 0.0);
+  for (int i = 0; i < 2 * m - 1; ++i) {
+    const double o = (double)(i - m + 1);
+    P->rc[i] = std::exp(-P->beta * (2.0 * o + 1.0));
+  }
+  // slab: k_v slices per pass of the 2D step
+  const size_t per_slice = ((size_t)P->M1 * p.n2 + (size_t)P->M1 * P->M2) * P->csize;
+  int S = p.slab;
+  if (S <= 0) {
+    S = 1;
+    while (S * 2 <= p.h && per_slice * S * 2 <= ((size_t)256 << 20)) S *= 2;
+  }
+  if (S > p.h) S = p.h;
+  P->slab = S;
+  // workspace layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+  P->off_tw = take((size_t)P->Ntw * P->csize);
+  P->off_cz = take((size_t)p.n0 * P->rsize);
+  P->off_cy = take((size_t)p.n1 * P->rsize);
+  P->off_cx = take((size_t)p.n2 * P->rsize);
+  P->off_zbase = take((size_t)p.h * sizeof(int));
+  P->off_zw = take((size_t)p.h * 2 * m * P->rsize);
+  P->off_cth = take((size_t)p.ntheta * sizeof(double));
+  P->off_sth = take((size_t)p.ntheta * sizeof(double));
+  P->off_rc = take(16 * sizeof(double));
+  P->off_u1 = take((size_t)p.h * p.n1 * p.n2 * P->csize);
+  P->off_p = take((size_t)p.ntheta * p.h * p.w * P->csize);
+  P->off_t = take((size_t)S * P->M1 * p.n2 * P->csize);
+  P->off_g = take((size_t)S * P->M1 * P->M2 * P->csize);
+  P->ws_need = o;
+  // kernel dimensions
+  Dims& D = P->D;
+  D.n0 = p.n0; D.n1 = p.n1; D.n2 = p.n2; D.h = p.h; D.w = p.w; D.ntheta = p.ntheta; D.m = m;
+  D.log2M0 = ilog2(P->M0); D.log2M1 = ilog2(P->M1); D.log2M2 = ilog2(P->M2);
+  D.beta = P->beta;
+  D.xy.Rn2 = (double)R * p.n2;
+  D.xy.Rn1 = (double)R * p.n1;
+  D.xy.inv_w = 1.0 / p.w;
+  D.xy.inv_h = 1.0 / p.h;
+  D.xy.sphi = std::sin(p.phi);
+  D.xy.w = p.w;
+  D.xy.h = p.h;
+  // launch shapes
+  LaunchCfg& c = P->cfg;
+  col_cfg(D.log2M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds);
+  col_cfg(D.log2M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
+  row_cfg(D.log2M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
+  row_cfg(ilog2(p.w), p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
+  col_cfg(ilog2(p.h), p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
+  const int TS = std::min(64, std::min(P->M1, P->M2));
+  c.g_log2TS = ilog2(TS);
+  c.g_threads = 256;
+  const size_t ints = (2 * (size_t)p.ntheta + 1 + 2 * 256) * sizeof(int);
+  const size_t Pt = TS + 2 * m - 1;
+  c.g_lds = align_up(Pt * Pt * P->csize, 16) + ints;
+  c.s_lds = align_up((size_t)TS * (TS + 1) * P->csize, 16) + ints;
+  if (c.g_lds > kLdsMax || c.s_lds > kLdsMax) return fail(LAM_ERR_ARG, "ntheta too large for the tile kernels' LDS");
+  return LAM_OK;
+}
+
+template <typename T>
+Tables<T> tables(const lam_plan_s* P) {
+  Tables<T> t;
+  unsigned char* w = P->ws;
+  t.tw = reinterpret_cast<const cpx<T>*>(w + P->off_tw);
+  t.log2tw = ilog2(P->Ntw);
+  t.cz = reinterpret_cast<const T*>(w + P->off_cz);
+  t.cy = reinterpret_cast<const T*>(w + P->off_cy);
+  t.cx = reinterpret_cast<const T*>(w + P->off_cx);
+  t.zbase = reinterpret_cast<const int*>(w + P->off_zbase);
+  t.zw = reinterpret_cast<const T*>(w + P->off_zw);
+  t.cth = reinterpret_cast<const double*>(w + P->off_cth);
+  t.sth = reinterpret_cast<const double*>(w + P->off_sth);
+  t.rc = reinterpret_cast<const double*>(w + P->off_rc);
+  return t;
+}
+
+template <typename T>
+std::vector<unsigned char> pack(const std::vector<double>& v) {
+  std::vector<unsigned char> out(v.size() * sizeof(T));
+  T* o = reinterpret_cast<T*>(out.data());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+  return out;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LAM_OK;
+  return fail(LAM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_ready(const lam_plan_s* P) {
+  if (!P) return fail(LAM_ERR_ARG, "null plan");
+  if (!P->ws) return fail(LAM_ERR_WORKSPACE, "no workspace set (call lam_set_workspace)");
+  return LAM_OK;
+}
+
+enum { K_ZFWD, K_YCOL_FWD, K_XROW_FWD, K_GATHER, K_ROWFFT, K_COLFFT, K_SCATTER, K_XROW_ADJ, K_YCOL_ADJ, K_ZADJ };
+const char* const kKernelNames[LAM_NUM_KERNELS] = {"zfwd", "ycol_fwd", "xrow_fwd", "gather", "rowfft",
+                                                  "colfft", "scatter", "xrow_adj", "ycol_adj", "zadj"};
+
+hipEvent_t take_event(lam_plan_s* P) {
+  if (!P->ev_pool.empty()) { hipEvent_t e = P->ev_pool.back(); P->ev_pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch one kernel; with profiling on, bracket it with events on its stream.
+template <class F>
+int timed(lam_plan_s* P, int slot, hipStream_t s, const char* what, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (P->prof_on) {
+    a = take_event(P);
+    b = take_event(P);
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) return fail(LAM_ERR_HIP, "profiling event");
+  }
+  const hipError_t e = launch();
+  if (P->prof_on) {
+    if (hipEventRecord(b, s) != hipSuccess) return fail(LAM_ERR_HIP, "profiling event");
+    P->recs.push_back({slot, a, b});
+  }
+  return hip_status(e, what);
+}
+
+// ---------------------------------------------------------------- operators
+template <typename T>
+int run_fwd(lam_plan_s* P, const void* u, bool real_in, const void* dhat, void* out, bool to_space, hipStream_t s) {
+  const Tables<T> tb = tables<T>(P);
+  const LaunchCfg& c = P->cfg;
+  const Dims& D = P->D;
+  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(P->ws + P->off_u1);
+  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(P->ws + P->off_t);
+  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
+  cpx<T>* o = reinterpret_cast<cpx<T>*>(out);
+  const cpx<T>* dh = reinterpret_cast<const cpx<T>*>(dhat);
+  int rc = timed(P, K_ZFWD, s, "F_u1D", [&] { return launch_zfwd<T>(c, u, real_in, U1, D, tb, s); });
+  for (int k0 = 0; !rc && k0 < P->p.h; k0 += P->slab) {
+    const int ns = std::min(P->slab, P->p.h - k0);
+    rc = timed(P, K_YCOL_FWD, s, "F_u2D y-FFT", [&] { return launch_ycol_fwd<T>(c, U1, Tb, k0, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_XROW_FWD, s, "F_u2D x-FFT", [&] { return launch_xrow_fwd<T>(c, Tb, Gb, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_GATHER, s, "F_u2D gather", [&] { return launch_gather<T>(c, Gb, o, dh, k0, ns, D, tb, s); });
+  }
+  if (!rc && to_space) {
+    rc = timed(P, K_ROWFFT, s, "F*_2D rows", [&] { return launch_rowfft<T>(c, o, o, true, D, tb, s); });
+    if (!rc) rc = timed(P, K_COLFFT, s, "F*_2D columns", [&] { return launch_colfft<T>(c, o, o, true, D, tb, s); });
+  }
+  return rc;
+}
+
+template <typename T>
+int run_adj(lam_plan_s* P, const void* in, bool from_space, void* u, bool real_out, hipStream_t s) {
+  const Tables<T> tb = tables<T>(P);
+  const LaunchCfg& c = P->cfg;
+  const Dims& D = P->D;
+  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(P->ws + P->off_u1);
+  cpx<T>* Pb = reinterpret_cast<cpx<T>*>(P->ws + P->off_p);
+  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(P->ws + P->off_t);
+  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
+  const cpx<T>* r = reinterpret_cast<const cpx<T>*>(in);
+  int rc = 0;
+  if (from_space) {
+    rc = timed(P, K_ROWFFT, s, "F_2D rows", [&] { return launch_rowfft<T>(c, r, Pb, false, D, tb, s); });
+    if (!rc) rc = timed(P, K_COLFFT, s, "F_2D columns", [&] { return launch_colfft<T>(c, Pb, Pb, false, D, tb, s); });
+    r = Pb;
+  }
+  for (int k0 = 0; !rc && k0 < P->p.h; k0 += P->slab) {
+    const int ns = std::min(P->slab, P->p.h - k0);
+    rc = timed(P, K_SCATTER, s, "F*_u2D scatter", [&] { return launch_scatter<T>(c, r, Gb, k0, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_XROW_ADJ, s, "F*_u2D x-FFT", [&] { return launch_xrow_adj<T>(c, Gb, Tb, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_YCOL_ADJ, s, "F*_u2D y-FFT", [&] { return launch_ycol_adj<T>(c, Tb, U1, k0, ns, D, tb, s); });
+  }
+  if (!rc) rc = timed(P, K_ZADJ, s, "F*_u1D", [&] { return launch_zadj<T>(c, U1, u, real_out, D, tb, s); });
+  return rc;
+}
+
+int fwd_any(lam_plan p, const void* u, bool real_in, const void* dhat, void* out, bool to_space, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!u || !out) return fail(LAM_ERR_ARG, "null array pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return p->p.dtype == LAM_C64 ? run_fwd<float>(p, u, real_in, dhat, out, to_space, s)
+                               : run_fwd<double>(p, u, real_in, dhat, out, to_space, s);
+}
+
+int adj_any(lam_plan p, const void* in, bool from_space, void* u, bool real_out, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!in || !u) return fail(LAM_ERR_ARG, "null array pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return p->p.dtype == LAM_C64 ? run_adj<float>(p, in, from_space, u, real_out, s)
+                               : run_adj<double>(p, in, from_space, u, real_out, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- internal
+namespace lam {
+// Accessors used by the ADMM step (same library).
+void* plan_ws(lam_plan p, size_t* off_p) { *off_p = p->off_p; return p->ws; }
+const lam_params& plan_params(lam_plan p) { return p->p; }
+int plan_fwd_hat_real(lam_plan p, const void* u, const void* dhat, void* r, hipStream_t s) {
+  return fwd_any(p, u, true, dhat, r, false, s);
+}
+int plan_adj_hat_real(lam_plan p, const void* r, void* u, hipStream_t s) { return adj_any(p, r, false, u, true, s); }
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace lam
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+int lam_init(lam_plan* out, const lam_params* p) {
+  g_last_error.clear();
+  if (!out || !p) return fail(LAM_ERR_ARG, "null argument");
+  *out = nullptr;
+  const char* bad = nullptr;
+  if (!is_pow2_in(p->n0, 16, 4096) || !is_pow2_in(p->n1, 16, 4096) || !is_pow2_in(p->n2, 16, 4096))
+    bad = "n0, n1, n2 must be powers of two in [16, 4096]";
+  else if (!is_pow2_in(p->h, 16, 4096) || !is_pow2_in(p->w, 16, 4096))
+    bad = "h, w must be powers of two in [16, 4096]";
+  else if (p->ntheta < 1 || p->ntheta > 8192) bad = "ntheta must be in [1, 8192]";
+  else if (!(p->phi >= 0.0 && p->phi < M_PI / 2)) bad = "phi must be in [0, pi/2)";
+  else if (p->oversample != 2) bad = "oversample must be 2";
+  else if (p->m < 1 || p->m > 8) bad = "m must be in [1, 8]";
+  else if (p->dtype != LAM_C64 && p->dtype != LAM_C128) bad = "dtype must be LAM_C64 or LAM_C128";
+  else if (p->slab < 0) bad = "slab must be >= 0";
+  if (bad) return fail(LAM_ERR_ARG, bad);
+  lam_plan_s* P = new (std::nothrow) lam_plan_s();
+  if (!P) return fail(LAM_ERR_NOMEM, "plan allocation failed");
+  try {
+    P->p = *p;
+    P->theta.resize(p->ntheta);
+    for (int t = 0; t < p->ntheta; ++t) {
+      P->theta[t] = p->theta ? p->theta[t] : 2.0 * M_PI * (double)t / (double)p->ntheta;
+      if (!std::isfinite(P->theta[t])) { delete P; return fail(LAM_ERR_ARG, "theta must be finite"); }
+    }
+    P->p.theta = nullptr;
+    const int rc = build(P);
+    if (rc) { delete P; return rc; }
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return fail(LAM_ERR_NOMEM, "host table allocation failed");
+  }
+  *out = P;
+  return LAM_OK;
+}
+
+size_t lam_workspace_bytes(lam_plan p) { return p ? p->ws_need : 0; }
+
+int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes) {
+  g_last_error.clear();
+  if (!p) return fail(LAM_ERR_ARG, "null plan");
+  if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) return fail(LAM_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < p->ws_need) return fail(LAM_ERR_WORKSPACE, "workspace smaller than lam_workspace_bytes");
+  unsigned char* w = static_cast<unsigned char*>(dev_ptr);
+  std::vector<std::pair<size_t, std::vector<unsigned char>>> blobs;
+  const bool f = p->p.dtype == LAM_C64;
+  blobs.emplace_back(p->off_tw, f ? pack<float>(p->tw) : pack<double>(p->tw));
+  blobs.emplace_back(p->off_cz, f ? pack<float>(p->cz) : pack<double>(p->cz));
+  blobs.emplace_back(p->off_cy, f ? pack<float>(p->cy) : pack<double>(p->cy));
+  blobs.emplace_back(p->off_cx, f ? pack<float>(p->cx) : pack<double>(p->cx));
+  blobs.emplace_back(p->off_zw, f ? pack<float>(p->zw) : pack<double>(p->zw));
+  blobs.emplace_back(p->off_cth, pack<double>(p->cth));
+  blobs.emplace_back(p->off_sth, pack<double>(p->sth));
+  blobs.emplace_back(p->off_rc, pack<double>(p->rc));
+  {
+    std::vector<unsigned char> zb(p->zbase.size() * sizeof(int));
+    std::memcpy(zb.data(), p->zbase.data(), zb.size());
+    blobs.emplace_back(p->off_zbase, std::move(zb));
+  }
+  for (auto& b : blobs) {
+    const hipError_t e = hipMemcpy(w + b.first, b.second.data(), b.second.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(LAM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e));
+  }
+  p->ws = w;
+  p->ws_bytes = bytes;
+  return LAM_OK;
+}
+
+int lam_fwd(lam_plan p, const void* u, void* d, void* s) { g_last_error.clear(); return fwd_any(p, u, false, nullptr, d, true, s); }
+int lam_adj(lam_plan p, const void* d, void* u, void* s) { g_last_error.clear(); return adj_any(p, d, true, u, false, s); }
+int lam_fwd_real(lam_plan p, const void* u, void* d, void* s) { g_last_error.clear(); return fwd_any(p, u, true, nullptr, d, true, s); }
+int lam_adj_real(lam_plan p, const void* d, void* u, void* s) { g_last_error.clear(); return adj_any(p, d, true, u, true, s); }
+int lam_fwd_hat(lam_plan p, const void* u, const void* dhat, void* r, void* s) {
+  g_last_error.clear();
+  return fwd_any(p, u, false, dhat, r, false, s);
+}
+int lam_adj_hat(lam_plan p, const void* r, void* u, void* s) { g_last_error.clear(); return adj_any(p, r, false, u, false, s); }
+
+int lam_profile(lam_plan p, int on) {
+  if (!p) return fail(LAM_ERR_ARG, "null plan");
+  p->prof_on = on != 0;
+  return LAM_OK;
+}
+
+int lam_profile_read(lam_plan p, double* total_ms, long long* launches) {
+  if (!p || !total_ms || !launches) return fail(LAM_ERR_ARG, "null argument");
+  for (int k = 0; k < LAM_NUM_KERNELS; ++k) { total_ms[k] = 0.0; launches[k] = 0; }
+  int rc = LAM_OK;
+  for (auto& r : p->recs) {
+    float ms = 0.f;
+    if (rc == LAM_OK) {
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess) rc = fail(LAM_ERR_HIP, std::string("profile read: ") + hipGetErrorString(e));
+    }
+    total_ms[r.slot] += ms;
+    launches[r.slot] += 1;
+    p->ev_pool.push_back(r.a);
+    p->ev_pool.push_back(r.b);
+  }
+  p->recs.clear();
+  return rc;
+}
+
+const char* lam_kernel_name(int k) { return (k >= 0 && k < LAM_NUM_KERNELS) ? kKernelNames[k] : ""; }
+
+void lam_destroy(lam_plan p) { delete p; }
+
+const char* lam_error_string(int code) {
+  switch (code) {
+    case LAM_OK: return "success";
+    case LAM_ERR_ARG: return "invalid argument";
+    case LAM_ERR_NOMEM: return "out of host memory";
+    case LAM_ERR_HIP: return "HIP runtime error";
+    case LAM_ERR_WORKSPACE: return "workspace missing or too small";
+    case LAM_ERR_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* lam_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Device building blocks for gfx950: complex arithmetic, an in-LDS batched
+// Stockham FFT (radix 8/4/2), and the Gaussian-gridding stencil.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lam {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+template <typename T> __device__ __forceinline__ cpx<T> mk(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cpx<T> operator*(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.x, -a.y); }
+// a * (-i)
+template <typename T> __device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return mk(a.y, -a.x); }
+
+// ---------------------------------------------------------------------------
+// Forward DFT butterflies (exponent sign -), natural-order outputs.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ void dft2(cpx<T>* v) {
+  cpx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T> __device__ __forceinline__ void dft4(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+  cpx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_mi(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <typename T> __device__ __forceinline__ void dft4(cpx<T>* v) { dft4(v[0], v[1], v[2], v[3]); }
+
+template <typename T> __device__ __forceinline__ void dft8(cpx<T>* v) {
+  const T r = (T)0.70710678118654752440084436210484904;
+  cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cpx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  o1 = mk((o1.x + o1.y) * r, (o1.y - o1.x) * r);     // * e^{-i pi/4}
+  o2 = mul_mi(o2);                                  // * e^{-i pi/2}
+  o3 = mk((o3.y - o3.x) * r, -(o3.x + o3.y) * r);    // * e^{-3 i pi/4}
+  v[0] = e0 + o0; v[4] = e0 - o0;
+  v[1] = e1 + o1; v[5] = e1 - o1;
+  v[2] = e2 + o2; v[6] = e2 - o2;
+  v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+template <typename T, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 4) dft4(v);
+  else dft8(v);
+}
+
+// ---------------------------------------------------------------------------
+// Batched in-place Stockham FFT in LDS.
+//
+// Element (point p, batch b) lives at buf[p*sp + b*sb].  N = 2^log2n points,
+// NB = 2^log2nb transforms.  Each radix-R stage reads every value into
+// registers, synchronises, applies twiddles and the R-point DFT and writes
+// the results to their autosorted positions, then synchronises again, so
+// one buffer suffices.  Values per thread per stage = N*NB/nthreads, which
+// must not exceed VPT.  tw[t] = exp(-2 pi i t / 2^log2tw), 2^log2tw >= N,
+// generated in FP64 on the host and rounded to T.  bfast selects the thread
+// to (j, b) map: batch index fastest (for interleaved [p][b] layouts) or
+// butterfly index fastest (for contiguous rows).
+// ---------------------------------------------------------------------------
+template <typename T, int R, int VPT>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, int Ns, int log2span, int sp, int sb,
+                                          bool bfast, const cpx<T>* __restrict__ tw, int log2tw) {
+  constexpr int IT = VPT / R;
+  constexpr int LR = (R == 8) ? 3 : (R == 4 ? 2 : 1);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int log2nbf = log2n - LR;                      // butterflies per transform = N / R
+  const int total = 1 << (log2nbf + log2nb);
+  const int nbf = 1 << log2nbf;
+  cpx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * nth;
+    if (t < total) {
+      int j, b;
+      if (bfast) { b = t & ((1 << log2nb) - 1); j = t >> log2nb; }
+      else { j = t & (nbf - 1); b = t >> log2nbf; }
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * nbf) * sp + b * sb];
+    }
+  }
+  __syncthreads();
+  const int twsh = log2tw - log2span;                  // span = Ns * R
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * nth;
+    if (t < total) {
+      int j, b;
+      if (bfast) { b = t & ((1 << log2nb) - 1); j = t >> log2nb; }
+      else { j = t & (nbf - 1); b = t >> log2nbf; }
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[(r * k) << twsh]);
+      dftR<T, R>(v[it]);
+      const int idxD = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(idxD + r * Ns) * sp + b * sb] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int VPT>
+__device__ __forceinline__ void lds_fft(cpx<T>* buf, int log2n, int log2nb, int sp, int sb, bool bfast,
+                        const cpx<T>* __restrict__ tw, int log2tw) {
+  int Ns = 1, lspan = 0, rem = log2n;
+  while (rem > 0) {
+    if (rem >= 3) {
+      fft_stage<T, 8, VPT>(buf, log2n, log2nb, Ns, lspan + 3, sp, sb, bfast, tw, log2tw);
+      Ns <<= 3; lspan += 3; rem -= 3;
+    } else if (rem == 2) {
+      fft_stage<T, 4, VPT>(buf, log2n, log2nb, Ns, lspan + 2, sp, sb, bfast, tw, log2tw);
+      Ns <<= 2; lspan += 2; rem -= 2;
+    } else {
+      fft_stage<T, 2, VPT>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw);
+      Ns <<= 1; lspan += 1; rem -= 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian-gridding stencil: for s = R xi (FP64), base = floor(s),
+// delta = s - base and the 2m weights exp(-beta (delta - o)^2),
+// o = -m+1 .. m, by the two-exponential recurrence
+//   w_{o+1} = w_o * exp(2 beta delta) * exp(-beta (2o + 1))
+// (Greengard & Lee 2004, fast Gaussian gridding), all in FP64, rounded to T.
+// rc[i] = exp(-beta (2 o_i + 1)) for o_i = -m+1+i, precomputed on the host.
+// ---------------------------------------------------------------------------
+template <typename T, int MH>
+__device__ __forceinline__ void stencil_weights(double s, double beta, const double* rc, int& base, T* w) {
+  const double b = floor(s);
+  const double d = s - b;
+  base = (int)b;
+  const double o0 = (double)(1 - MH);
+  double cur = exp(-beta * (d - o0) * (d - o0));
+  const double e = exp(2.0 * beta * d);
+  w[0] = (T)cur;
+#pragma unroll
+  for (int i = 1; i < 2 * MH; ++i) {
+    cur = cur * e * rc[i - 1];
+    w[i] = (T)cur;
+  }
+}
+
+// Oversampled coordinates (R n nu) of detector bin (k_v, k_u) at angle with
+// cos/sin (ct, st): the same expression in the forward gather and the
+// adjoint scatter, so both see identical bases and weights.
+struct XYGeom {
+  double Rn2, Rn1;        // R * n2, R * n1
+  double inv_w, inv_h;    // 1/w, 1/h
+  double sphi;            // sin(phi)
+  int w, h;
+};
+
+// Contraction is off so the coordinate is the plain sequence of correctly
+// rounded products and sums: at angles where s lands on an integer (multiples
+// of pi/2), a fused multiply-add would round differently and move floor(s).
+__device__ __forceinline__ void target_coords(const XYGeom& g, double ct, double st, int akv, int aku,
+                                              double& sx, double& sy) {
+#pragma clang fp contract(off)
+  const double ku = (double)(aku - g.w / 2) * g.inv_w;
+  const double kv = (double)(akv - g.h / 2) * g.inv_h;
+  sx = g.Rn2 * (ku * ct + kv * g.sphi * st);
+  sy = g.Rn1 * (ku * st - kv * g.sphi * ct);
+}
+
+}  // namespace lam

@@ -1,0 +1,74 @@
+// Internal declarations shared by the kernels and the host plan.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lam_device.hpp"
+
+namespace lam {
+
+// Sizes passed by value to every kernel.
+struct Dims {
+  int n0, n1, n2, h, w, ntheta, m;
+  int log2M0, log2M1, log2M2;
+  double beta;      // Gaussian exponent in grid units, pi (R - 1/2) / (R m)
+  XYGeom xy;
+};
+
+// Device tables (inside the caller's workspace), built in FP64 on the host.
+template <typename T>
+struct Tables {
+  const cpx<T>* tw;   // exp(-2 pi i t / 2^log2tw)
+  int log2tw;
+  const T* cz;        // deconvolution factors along z, y, x
+  const T* cy;
+  const T* cx;
+  const int* zbase;   // [h] floor(R xi_z)
+  const T* zw;        // [h][2m] z-gather weights
+  const double* cth;  // [ntheta] cos(theta)
+  const double* sth;  // [ntheta] sin(theta)
+  const double* rc;   // [2m] exp(-beta (2 o + 1)), o = -m+1 ..
+};
+
+// Launch shapes chosen by the host plan.
+struct LaunchCfg {
+  int z_log2TX, z_threads; size_t z_lds;    // F_u1D column blocks
+  int y_log2TX, y_threads; size_t y_lds;    // y-FFT column blocks
+  int x_log2RB, x_threads; size_t x_lds;    // x-FFT row blocks
+  int g_log2TS, g_threads; size_t g_lds;    // gather tiles
+  size_t s_lds;                             // scatter tiles
+  int r_log2RB, r_threads; size_t r_lds;    // 2D FFT row pass
+  int c_log2TX, c_threads; size_t c_lds;    // 2D FFT column pass
+};
+
+template <typename T>
+hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, const Dims& D, const Tables<T>& tb,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, const Dims& D,
+                       const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_ycol_fwd(const LaunchCfg& c, const cpx<T>* u1, cpx<T>* Tb, int k0, int ns, const Dims& D,
+                           const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_xrow_fwd(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* Gb, int ns, const Dims& D,
+                           const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* out, const cpx<T>* dhat, int k0, int ns,
+                         const Dims& D, const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int k0, int ns, const Dims& D,
+                          const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_xrow_adj(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* Tb, int ns, const Dims& D,
+                           const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_ycol_adj(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* u1, int k0, int ns, const Dims& D,
+                           const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
+                         const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
+                         const Tables<T>& tb, hipStream_t s);
+
+}  // namespace lam

@@ -103,6 +103,18 @@ def blob_phantom_torch(shape, blobs: BlobSet, device, dtype):
     return u.to(dtype)
 
 
+def random_complex_torch(shape, seed: int, device, dtype):
+    """Seeded i.i.d. N(0,1) real and imaginary parts drawn on ``device`` (torch generator)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    re = torch.randn(shape, generator=g, device=device, dtype=rdt)
+    im = torch.randn(shape, generator=g, device=device, dtype=rdt)
+    return torch.complex(re, im)
+
+
 def random_complex(shape, seed: int) -> np.ndarray:
     """i.i.d. N(0,1) real and imaginary parts, complex128."""
     rng = np.random.default_rng(seed)

@@ -1,0 +1,234 @@
+"""Python binding of liblam.so: argument marshalling only.
+
+Every step of the operator runs in the HIP kernels of liblam.so; PyTorch only
+supplies device memory (the workspace and the arrays) and the stream.  If
+the library is not built, or no GPU is present, these calls raise: there is
+no CPU fallback.
+
+    plan = Plan(512, ntheta=512, phi=math.radians(30), h=512, w=512)
+    d = plan.fwd(u)              # L u          (u complex or real)
+    v = plan.adj(d)              # L* d         (complex; plan.adj(d, real=True) -> Re)
+    r = plan.fwd_hat(u, dhat)    # L^ u - d^    (Algorithm 2, fused subtraction)
+    w = plan.adj_hat(r)          # L^* r
+    y = LamOp.apply(u, plan)     # autograd: backward is the adjoint kernel
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_size_t, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblam.so")
+
+LAM_C64, LAM_C128 = 0, 1
+STATUS = {0: "LAM_OK", 1: "LAM_ERR_ARG", 2: "LAM_ERR_NOMEM", 3: "LAM_ERR_HIP", 4: "LAM_ERR_WORKSPACE",
+          5: "LAM_ERR_STATE"}
+
+
+class LamError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        super().__init__(f"{STATUS.get(code, code)}: {detail}")
+        self.code = code
+
+
+class LamParams(ctypes.Structure):
+    _fields_ = [
+        ("n0", c_int), ("n1", c_int), ("n2", c_int),
+        ("ntheta", c_int),
+        ("theta", POINTER(c_double)),
+        ("phi", c_double),
+        ("h", c_int), ("w", c_int),
+        ("oversample", c_int),
+        ("m", c_int),
+        ("dtype", c_int),
+        ("slab", c_int),
+    ]
+
+
+class AdmmState(ctypes.Structure):
+    _fields_ = [("u", c_void_p), ("psi", c_void_p), ("lam", c_void_p), ("work", c_void_p),
+                ("scal", POINTER(c_double))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblam.so (built in-tree by paper_2511_01893_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_01893_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.lam_init.argtypes = [POINTER(c_void_p), POINTER(LamParams)]
+        L.lam_workspace_bytes.argtypes = [c_void_p]
+        L.lam_workspace_bytes.restype = c_size_t
+        L.lam_set_workspace.argtypes = [c_void_p, c_void_p, c_size_t]
+        for name in ("lam_fwd", "lam_adj", "lam_fwd_real", "lam_adj_real", "lam_adj_hat"):
+            getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        L.lam_fwd_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.lam_admm_work_bytes.argtypes = [c_void_p]
+        L.lam_admm_work_bytes.restype = c_size_t
+        L.lam_admm_step.argtypes = [c_void_p, POINTER(AdmmState), c_void_p, c_int, c_void_p]
+        L.lam_profile.argtypes = [c_void_p, c_int]
+        L.lam_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(ctypes.c_longlong)]
+        L.lam_kernel_name.argtypes = [c_int]
+        L.lam_kernel_name.restype = ctypes.c_char_p
+        L.lam_destroy.argtypes = [c_void_p]
+        L.lam_destroy.restype = None
+        L.lam_error_string.argtypes = [c_int]
+        L.lam_error_string.restype = ctypes.c_char_p
+        L.lam_last_error.argtypes = []
+        L.lam_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LamError(rc, lib().lam_last_error().decode())
+
+
+class Plan:
+    """Operator plan: problem statement + device workspace (owned by torch)."""
+
+    def __init__(self, n0: int, n1: int | None = None, n2: int | None = None, *, ntheta: int, phi: float,
+                 h: int | None = None, w: int | None = None, m: int = 4, oversample: int = 2,
+                 dtype: torch.dtype = torch.complex64, slab: int = 0, theta=None, device="cuda"):
+        n1 = n0 if n1 is None else n1
+        n2 = n0 if n2 is None else n2
+        h = n0 if h is None else h
+        w = n2 if w is None else w
+        if dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        self.n0, self.n1, self.n2, self.ntheta, self.phi, self.h, self.w = n0, n1, n2, ntheta, phi, h, w
+        self.m, self.oversample, self.dtype = m, oversample, dtype
+        self.rdtype = torch.float32 if dtype == torch.complex64 else torch.float64
+        self.device = torch.device(device)
+        self._theta = None
+        p = LamParams(n0, n1, n2, ntheta, None, float(phi), h, w, oversample, m,
+                      LAM_C64 if dtype == torch.complex64 else LAM_C128, slab)
+        if theta is not None:
+            self._theta = (c_double * ntheta)(*[float(t) for t in theta])
+            p.theta = ctypes.cast(self._theta, POINTER(c_double))
+        self._h = c_void_p()
+        _check(lib().lam_init(byref(self._h), byref(p)))
+        nbytes = lib().lam_workspace_bytes(self._h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _check(lib().lam_set_workspace(self._h, c_void_p(self.workspace.data_ptr()), nbytes))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lam_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- shapes
+    @property
+    def vol_shape(self):
+        return (self.n0, self.n1, self.n2)
+
+    @property
+    def data_shape(self):
+        return (self.ntheta, self.h, self.w)
+
+    def _stream(self):
+        return c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _arr(self, x: torch.Tensor, shape, what: str, allow_real=False) -> torch.Tensor:
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(x.shape)}")
+        if x.device != self.device and not (x.device.type == "cuda" and self.device.type == "cuda"
+                                            and (x.device.index or 0) == (self.device.index or 0)):
+            raise ValueError(f"{what}: expected a tensor on {self.device}, got {x.device}")
+        ok = (self.dtype,) + ((self.rdtype,) if allow_real else ())
+        if x.dtype not in ok:
+            raise ValueError(f"{what}: expected dtype in {ok}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{what}: tensor must be contiguous")
+        return x
+
+    # ---------------------------------------------------------------- operators
+    def fwd(self, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """d = L u (F*_2D F_u2D F_u1D); u complex or real."""
+        self._arr(u, self.vol_shape, "u", allow_real=True)
+        out = torch.empty(self.data_shape, dtype=self.dtype, device=self.device) if out is None else out
+        self._arr(out, self.data_shape, "d")
+        f = lib().lam_fwd if u.is_complex() else lib().lam_fwd_real
+        _check(f(self._h, c_void_p(u.data_ptr()), c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def adj(self, d: torch.Tensor, real: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+        """u = L* d (F*_u1D F*_u2D F_2D); real=True returns Re(L* d)."""
+        self._arr(d, self.data_shape, "d")
+        dt = self.rdtype if real else self.dtype
+        out = torch.empty(self.vol_shape, dtype=dt, device=self.device) if out is None else out
+        f = lib().lam_adj_real if real else lib().lam_adj
+        _check(f(self._h, c_void_p(d.data_ptr()), c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def fwd_hat(self, u: torch.Tensor, dhat: torch.Tensor | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        """r = L^ u - d^ (Algorithm 2, subtraction fused into F_u2D)."""
+        self._arr(u, self.vol_shape, "u")
+        if dhat is not None:
+            self._arr(dhat, self.data_shape, "dhat")
+        out = torch.empty(self.data_shape, dtype=self.dtype, device=self.device) if out is None else out
+        _check(lib().lam_fwd_hat(self._h, c_void_p(u.data_ptr()),
+                                 c_void_p(dhat.data_ptr() if dhat is not None else None),
+                                 c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def adj_hat(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """u = L^* r (exact adjoint of fwd_hat's linear part)."""
+        self._arr(r, self.data_shape, "r")
+        out = torch.empty(self.vol_shape, dtype=self.dtype, device=self.device) if out is None else out
+        _check(lib().lam_adj_hat(self._h, c_void_p(r.data_ptr()), c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+
+    # ---------------------------------------------------------------- timing
+    def profile(self, on: bool = True):
+        """Bracket every kernel of this plan with HIP events (for measurement)."""
+        _check(lib().lam_profile(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last read; waits for the events."""
+        n = NUM_KERNELS
+        ms = (c_double * n)()
+        cnt = (ctypes.c_longlong * n)()
+        _check(lib().lam_profile_read(self._h, ms, cnt))
+        return {lib().lam_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
+
+
+NUM_KERNELS = 10
+
+
+class LamOp(torch.autograd.Function):
+    """d = L u with backward = the hand-written adjoint kernel.
+
+    Complex u: PyTorch's conjugate-Wirtinger convention gives grad_u = L* g.
+    Real u: grad_u = Re(L* g).  L is linear, so nothing is saved."""
+
+    @staticmethod
+    def forward(ctx, u, plan: Plan):
+        ctx.plan = plan
+        ctx.real = not u.is_complex()
+        return plan.fwd(u.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.adj(g.contiguous(), real=ctx.real), None
+
+
+def plan_for(name: str, dtype=torch.complex64, device="cuda", slab: int = 0) -> Plan:
+    """Plan for one of the named workloads (see paper_2511_01893_amd.inputs.WORKLOADS)."""
+    from .inputs import WORKLOADS
+
+    w = WORKLOADS[name]
+    return Plan(w["n"], ntheta=w["ntheta"], phi=math.radians(w["phi_deg"]), h=w["det"], w=w["det"], dtype=dtype,
+                device=device, slab=slab)

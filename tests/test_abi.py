@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU compute): the library loads, exports
+every function include/lam.h declares, validates its arguments, reports
+workspace sizes and error strings."""
+import ctypes
+import math
+import os
+import re
+from ctypes import byref, c_void_p
+
+import pytest
+
+from paper_2511_01893_amd import lam as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "lam.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lam_[a-z_]+)\s*\(", txt)))
+
+
+def _params(**kw):
+    d = dict(n0=32, n1=32, n2=32, ntheta=32, theta=None, phi=math.radians(20), h=32, w=32, oversample=2, m=4,
+             dtype=0, slab=0)
+    d.update(kw)
+    return L.LamParams(d["n0"], d["n1"], d["n2"], d["ntheta"], d["theta"], d["phi"], d["h"], d["w"],
+                       d["oversample"], d["m"], d["dtype"], d["slab"])
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _header_functions()
+    assert "lam_fwd" in names and "lam_admm_step" in names and len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layout_matches_header():
+    # int n0,n1,n2,ntheta; double* theta; double phi; int h,w,oversample,m,dtype,slab
+    assert L.LamParams.theta.offset == 16 and L.LamParams.phi.offset == 24
+    assert L.LamParams.h.offset == 32 and L.LamParams.slab.offset == 52
+    assert ctypes.sizeof(L.LamParams) == 56
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n0=24), dict(n1=8), dict(n2=8192), dict(h=48), dict(w=0), dict(ntheta=0), dict(phi=math.pi / 2),
+    dict(phi=-0.1), dict(phi=float("nan")), dict(oversample=3), dict(m=0), dict(m=9), dict(dtype=2), dict(slab=-1),
+])
+def test_init_rejects_bad_parameters(bad):
+    h = c_void_p()
+    rc = L.lib().lam_init(byref(h), byref(_params(**bad)))
+    assert rc == 1
+    assert h.value is None
+    assert L.lib().lam_last_error().decode()
+
+
+def test_init_rejects_nonfinite_theta():
+    arr = (ctypes.c_double * 4)(0.0, 1.0, float("inf"), 2.0)
+    h = c_void_p()
+    rc = L.lib().lam_init(byref(h), byref(_params(ntheta=4, theta=ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))))
+    assert rc == 1
+
+
+def test_workspace_size_and_state_errors():
+    lib = L.lib()
+    h = c_void_p()
+    assert lib.lam_init(byref(h), byref(_params(dtype=0, slab=4))) == 0
+    nb = lib.lam_workspace_bytes(h)
+    # u1 (h n1 n2) + P (ntheta h w) + T (slab M1 n2) + G (slab M1 M2), complex64, plus small tables
+    big = (32 * 32 * 32 + 32 * 32 * 32 + 4 * 64 * 32 + 4 * 64 * 64) * 8
+    assert big <= nb <= big + 64 * 1024
+    h2 = c_void_p()
+    assert lib.lam_init(byref(h2), byref(_params(dtype=1, slab=4))) == 0
+    assert lib.lam_workspace_bytes(h2) > 2 * big - 1
+    # compute before a workspace is set
+    assert lib.lam_fwd(h, c_void_p(256), c_void_p(512), None) == 4
+    assert lib.lam_adj_hat(h, c_void_p(256), c_void_p(512), None) == 4
+    # misaligned / too small workspace
+    assert lib.lam_set_workspace(h, c_void_p(0x1001), nb) == 1
+    assert lib.lam_set_workspace(h, c_void_p(0x1000), nb - 1) == 4
+    assert lib.lam_set_workspace(h, c_void_p(None), nb) == 1
+    lib.lam_destroy(h)
+    lib.lam_destroy(h2)
+    lib.lam_destroy(None)
+
+
+def test_error_strings():
+    lib = L.lib()
+    for code in range(6):
+        assert lib.lam_error_string(code)
+    assert lib.lam_error_string(99) == b"unknown status"
+
+
+def test_null_arguments():
+    lib = L.lib()
+    assert lib.lam_init(None, byref(_params())) == 1
+    h = c_void_p()
+    assert lib.lam_init(byref(h), None) == 1
+    assert lib.lam_fwd(None, c_void_p(256), c_void_p(256), None) == 1
+    assert lib.lam_workspace_bytes(None) == 0
+
+
+@pytest.mark.skipif(__import__("torch").cuda.device_count() > 0, reason="needs a host without a GPU")
+def test_no_device_reports_hip_error():
+    """Without a GPU the table upload fails cleanly with LAM_ERR_HIP."""
+    lib = L.lib()
+    h = c_void_p()
+    assert lib.lam_init(byref(h), byref(_params())) == 0
+    assert lib.lam_set_workspace(h, c_void_p(0x100000), lib.lam_workspace_bytes(h)) == 3
+    assert lib.lam_last_error().decode()
+    lib.lam_destroy(h)

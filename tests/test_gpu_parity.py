@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: complex128 path <= 1e-12 relative L2 (same algorithm, rounding only);
+complex64 path <= 1e-4 relative L2 (the stated target; FP32 rounding of an
+FFT chain of this length gives ~1e-6); adjoint identity <= 1e-5 (c64) and
+<= 1e-12 (c128).  Sizes span several 64x64 tiles of the oversampled grid,
+ragged angle counts and ragged slabs; the oracle finishes each in seconds.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lam_oracle as O
+from paper_2511_01893_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex64: 1e-4, torch.complex128: 1e-12}
+ADJ_TOL = {torch.complex64: 1e-5, torch.complex128: 1e-12}
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_01893_amd import lam
+    lam.lib()
+    return lam
+
+
+def make(L, dtype, n0, n1, n2, ntheta, phi_deg, h, w, m=4, slab=0, theta=None):
+    plan = L.Plan(n0, n1, n2, ntheta=ntheta, phi=math.radians(phi_deg), h=h, w=w, m=m, dtype=dtype, slab=slab,
+                  theta=theta)
+    geo = O.Geometry(n0, n1, n2, ntheta, math.radians(phi_deg), h, w, 2, m, theta=theta)
+    return plan, geo
+
+
+def gpu(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def report(name, err, tol):
+    print(f"{name}: rel err {err:.3e} (bar {tol:.0e})", flush=True)
+    assert err <= tol, (name, err, tol)
+
+
+DTYPES = [torch.complex64, torch.complex128]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+def test_tiny32_all_entry_points(L, dtype):
+    w = I.WORKLOADS["tiny32"]
+    plan, geo = make(L, dtype, 32, 32, 32, 32, w["phi_deg"], 32, 32)
+    u = I.blob_phantom(geo.vol_shape, I.draw_blobs(w["seed"], w["nblobs"])).astype(np.complex128)
+    d = I.random_detector_data(geo.data_shape, w["seed"])
+    tol = TOL[dtype]
+    ug, dg = gpu(u, dtype), gpu(d, dtype)
+    report("fwd", O.relerr(host(plan.fwd(ug)), O.lam_fwd(u, geo)), tol)
+    report("adj", O.relerr(host(plan.adj(dg)), O.lam_adj(d, geo)), tol)
+    dhat = O.f2d_unnorm(d)
+    report("fwd_hat", O.relerr(host(plan.fwd_hat(ug)), O.lam_fwd_hat(u, geo)), tol)
+    report("fwd_hat-dhat", O.relerr(host(plan.fwd_hat(ug, gpu(dhat, dtype))), O.lam_fwd_hat(u, geo, dhat)), tol)
+    report("adj_hat", O.relerr(host(plan.adj_hat(gpu(dhat, dtype))), O.lam_adj_hat(dhat, geo)), tol)
+    ur = u.real.copy()
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    report("fwd_real", O.relerr(host(plan.fwd(torch.from_numpy(ur).to(rdt).cuda())), O.lam_fwd(ur, geo)), tol)
+    report("adj_real", O.relerr(host(plan.adj(dg, real=True)), O.lam_adj(d, geo).real), tol)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("case", [
+    dict(n0=16, n1=32, n2=64, ntheta=7, phi=35.0, h=32, w=16),          # every size different
+    dict(n0=64, n1=16, n2=32, ntheta=37, phi=10.0, h=16, w=64),         # ragged angle count
+    dict(n0=32, n1=32, n2=32, ntheta=12, phi=20.0, h=32, w=32, m=1),
+    dict(n0=32, n1=32, n2=32, ntheta=12, phi=20.0, h=32, w=32, m=2),
+    dict(n0=32, n1=32, n2=32, ntheta=12, phi=60.0, h=32, w=32, m=8),
+    dict(n0=32, n1=32, n2=32, ntheta=9, phi=25.0, h=32, w=32, slab=3),  # ragged last slab
+], ids=["rect", "ragged-theta", "m1", "m2", "m8-phi60", "slab3"])
+def test_geometries(L, dtype, case):
+    c = dict(case)
+    m, slab = c.pop("m", 4), c.pop("slab", 0)
+    plan, geo = make(L, dtype, c["n0"], c["n1"], c["n2"], c["ntheta"], c["phi"], c["h"], c["w"], m=m, slab=slab)
+    u = I.random_complex(geo.vol_shape, 5)
+    d = I.random_detector_data(geo.data_shape, 5)
+    tol = TOL[dtype]
+    report("fwd", O.relerr(host(plan.fwd(gpu(u, dtype))), O.lam_fwd(u, geo)), tol)
+    report("adj", O.relerr(host(plan.adj(gpu(d, dtype))), O.lam_adj(d, geo)), tol)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+def test_tomography_special_angles(L, dtype):
+    theta = [0.0, math.pi / 2, math.pi, 1.25 * math.pi, 0.3]
+    plan, geo = make(L, dtype, 32, 32, 32, 5, 0.0, 32, 32, m=4, theta=theta)
+    u = I.random_complex(geo.vol_shape, 6)
+    report("fwd", O.relerr(host(plan.fwd(gpu(u, dtype))), O.lam_fwd(u, geo)), TOL[dtype])
+    d = I.random_detector_data(geo.data_shape, 6)
+    report("adj", O.relerr(host(plan.adj(gpu(d, dtype))), O.lam_adj(d, geo)), TOL[dtype])
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+def test_several_tiles_128(L, dtype):
+    # oversampled grid 256 x 256 = 4 x 4 tiles of 64; 96 angles
+    plan, geo = make(L, dtype, 128, 128, 128, 96, 30.0, 128, 128)
+    bl = I.draw_blobs(7, 16)
+    u = I.blob_phantom(geo.vol_shape, bl).astype(np.complex128)
+    d = I.random_detector_data(geo.data_shape, 7)
+    tol = TOL[dtype]
+    report("fwd", O.relerr(host(plan.fwd(gpu(u, dtype))), O.lam_fwd(u, geo)), tol)
+    report("adj", O.relerr(host(plan.adj(gpu(d, dtype))), O.lam_adj(d, geo)), tol)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+def test_adjoint_identity(L, dtype):
+    plan, geo = make(L, dtype, 64, 64, 64, 64, 30.0, 64, 64)
+    u = gpu(I.random_complex(geo.vol_shape, 8), dtype)
+    d = gpu(I.random_detector_data(geo.data_shape, 8), dtype)
+    Lu, Lsd = plan.fwd(u), plan.adj(d)
+    err = O.adjoint_error(host(Lu), host(d), host(u), host(Lsd))
+    report("adjoint <Lu,d> - <u,L*d>", err, ADJ_TOL[dtype])
+    r = plan.fwd_hat(u)
+    err2 = O.adjoint_error(host(r), host(d), host(u), host(plan.adj_hat(d)))
+    report("adjoint hat", err2, ADJ_TOL[dtype])
+
+
+def test_slabs_are_equivalent(L):
+    p0, geo = make(L, torch.complex64, 64, 64, 64, 24, 30.0, 64, 64, slab=0)
+    p1, _ = make(L, torch.complex64, 64, 64, 64, 24, 30.0, 64, 64, slab=5)
+    u = gpu(I.random_complex(geo.vol_shape, 9), torch.complex64)
+    d = gpu(I.random_detector_data(geo.data_shape, 9), torch.complex64)
+    assert torch.equal(p0.fwd(u), p1.fwd(u))          # the gather is deterministic
+    a, b = p0.adj(d), p1.adj(d)
+    assert (a - b).abs().max().item() <= 1e-6 * a.abs().max().item()
+
+
+def test_fused_subtraction_in_place(L):
+    plan, geo = make(L, torch.complex64, 32, 32, 32, 16, 20.0, 32, 32)
+    u = gpu(I.random_complex(geo.vol_shape, 10), torch.complex64)
+    dhat = gpu(I.random_complex(geo.data_shape, 11), torch.complex64)
+    ref = plan.fwd_hat(u) - dhat
+    r = dhat.clone()
+    plan.fwd_hat(u, r, out=r)                          # r may alias dhat
+    assert (r - ref).abs().max().item() <= 1e-6 * ref.abs().max().item()
+
+
+def test_operator_is_linear(L):
+    plan, geo = make(L, torch.complex64, 32, 32, 32, 16, 20.0, 32, 32)
+    a = gpu(I.random_complex(geo.vol_shape, 12), torch.complex64)
+    b = gpu(I.random_complex(geo.vol_shape, 13), torch.complex64)
+    lhs = plan.fwd(a + (0.5 - 2j) * b)
+    rhs = plan.fwd(a) + (0.5 - 2j) * plan.fwd(b)
+    assert ((lhs - rhs).norm() / rhs.norm()).item() < 1e-5
+    z = torch.zeros_like(a)
+    assert plan.fwd(z).abs().max().item() == 0.0
+
+
+def test_streams_and_errors(L):
+    plan, geo = make(L, torch.complex64, 32, 32, 32, 8, 20.0, 32, 32)
+    u = gpu(I.random_complex(geo.vol_shape, 14), torch.complex64)
+    ref = plan.fwd(u)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = plan.fwd(u)
+    s.synchronize()
+    assert torch.equal(ref, out)
+    with pytest.raises(ValueError):
+        plan.fwd(u[:16])
+    with pytest.raises(ValueError):
+        plan.fwd(u.to(torch.complex128))
