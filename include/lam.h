@@ -129,15 +129,24 @@ int lam_fwd_hat(lam_plan p, const void* u, const void* dhat, void* r, void* hip_
  * r: complex (ntheta, h, w), read only; u: complex volume. */
 int lam_adj_hat(lam_plan p, const void* r, void* u, void* hip_stream);
 
+/* dhat = W d: the unnormalised centred 2D DFT of every projection, computed
+ * once before the LSP loop (Algorithm 2, "d^ <- F_2D d"); with this scaling
+ * |L u - d|^2 = |L^ u - d^|^2 / (h w).  d, dhat: complex (ntheta, h, w);
+ * they may be the same buffer. */
+int lam_data_hat(lam_plan p, const void* d, void* dhat, void* hip_stream);
+
 /* ADMM-TV state for lam_admm_step: all device pointers, caller-owned, real
  * arrays of the plan's real type (float for LAM_C64, double for LAM_C128).
  *   u      [n0 n1 n2]        reconstruction (updated)
  *   psi    [3][n0 n1 n2]     auxiliary variable psi ~ grad u (updated)
  *   lam    [3][n0 n1 n2]     multiplier lambda (updated)
  *   work   lam_admm_work_bytes(p) bytes of device scratch
- *   scal   device array of 8 doubles: scal[0] = rho (updated), scal[1] = alpha,
- *          scal[2..7] are written with diagnostics (last CG step, primal and
- *          dual residuals).  FP64 throughout. */
+ *   scal   device array of 8 doubles: scal[0] = rho (read, then updated by the
+ *          penalty rule), scal[1] = alpha (read); written with diagnostics:
+ *          scal[2] last CG step gamma, scal[3] primal residual |grad u - psi|,
+ *          scal[4] dual residual rho |grad^T(psi - psi_prev)|, scal[5] |G| of
+ *          the last CG step, scal[6] the rho this step used.  FP64 throughout.
+ * u, psi and lam are updated in place; start from zeros for a fresh solve. */
 typedef struct {
   void* u;
   void* psi;

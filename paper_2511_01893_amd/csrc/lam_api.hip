@@ -44,10 +44,11 @@ struct lam_plan_s {
   size_t csize = 8, rsize = 4;
   // host tables (FP64)
   std::vector<double> tw, cz, cy, cx, zw, cth, sth, rc;
-  std::vector<int> zbase;
+  std::vector<int> zbase, zq_ptr, zq_av;
+  std::vector<double> zq_w;
   // workspace layout (byte offsets)
   size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zw = 0, off_cth = 0, off_sth = 0,
-         off_rc = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
+         off_rc = 0, off_zq_ptr = 0, off_zq_av = 0, off_zq_w = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   Dims D{};
@@ -125,6 +126,23 @@ int build(lam_plan_s* P) {
       P->zw[(size_t)av * 2 * m + i] = std::exp(-P->beta * (d - o) * (d - o));
     }
   }
+  // inverse z table: for each oversampled grid point q, the (k_v, weight)
+  // pairs whose stencil covers q (the adjoint's gather form)
+  {
+    std::vector<std::vector<std::pair<int, double>>> rows(P->M0);
+    for (int av = 0; av < p.h; ++av)
+      for (int i = 0; i < 2 * m; ++i) {
+        const int q = (P->zbase[av] - m + 1 + i) & (P->M0 - 1);
+        rows[q].emplace_back(av, P->zw[(size_t)av * 2 * m + i]);
+      }
+    P->zq_ptr.assign(P->M0 + 1, 0);
+    P->zq_av.clear();
+    P->zq_w.clear();
+    for (int q = 0; q < P->M0; ++q) {
+      for (auto& e : rows[q]) { P->zq_av.push_back(e.first); P->zq_w.push_back(e.second); }
+      P->zq_ptr[q + 1] = (int)P->zq_av.size();
+    }
+  }
   P->cth.resize(p.ntheta);
   P->sth.resize(p.ntheta);
   for (int t = 0; t < p.ntheta; ++t) {
@@ -157,6 +175,9 @@ int build(lam_plan_s* P) {
   P->off_cth = take((size_t)p.ntheta * sizeof(double));
   P->off_sth = take((size_t)p.ntheta * sizeof(double));
   P->off_rc = take(16 * sizeof(double));
+  P->off_zq_ptr = take(((size_t)P->M0 + 1) * sizeof(int));
+  P->off_zq_av = take((size_t)p.h * 2 * m * sizeof(int));
+  P->off_zq_w = take((size_t)p.h * 2 * m * P->rsize);
   P->off_u1 = take((size_t)p.h * p.n1 * p.n2 * P->csize);
   P->off_p = take((size_t)p.ntheta * p.h * p.w * P->csize);
   P->off_t = take((size_t)S * P->M1 * p.n2 * P->csize);
@@ -177,6 +198,12 @@ int build(lam_plan_s* P) {
   // launch shapes
   LaunchCfg& c = P->cfg;
   col_cfg(D.log2M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds);
+  // the z adjoint stages h samples per column in the same LDS: shrink the tile if h > M0
+  while (c.z_log2TX > 0 && (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize > 131072) {
+    --c.z_log2TX;
+    c.z_threads = (int)std::max<long>(64, ((long)P->M0 << c.z_log2TX) / kVPT);
+  }
+  c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize;
   col_cfg(D.log2M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
   row_cfg(D.log2M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
   row_cfg(ilog2(p.w), p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
@@ -187,7 +214,9 @@ int build(lam_plan_s* P) {
   const size_t ints = (2 * (size_t)p.ntheta + 1 + 2 * 256) * sizeof(int);
   const size_t Pt = TS + 2 * m - 1;
   c.g_lds = align_up(Pt * Pt * P->csize, 16) + ints;
-  c.s_lds = align_up((size_t)TS * (TS + 1) * P->csize, 16) + ints;
+  // scatter: FP64 accumulator tile + candidate scan
+  c.s_threads = 256;
+  c.s_lds = (size_t)TS * (TS + 1) * 16 + (2 * (size_t)p.ntheta + 1 + 2 * 256) * sizeof(int);
   if (c.g_lds > kLdsMax || c.s_lds > kLdsMax) return fail(LAM_ERR_ARG, "ntheta too large for the tile kernels' LDS");
   return LAM_OK;
 }
@@ -206,6 +235,9 @@ Tables<T> tables(const lam_plan_s* P) {
   t.cth = reinterpret_cast<const double*>(w + P->off_cth);
   t.sth = reinterpret_cast<const double*>(w + P->off_sth);
   t.rc = reinterpret_cast<const double*>(w + P->off_rc);
+  t.zq_ptr = reinterpret_cast<const int*>(w + P->off_zq_ptr);
+  t.zq_av = reinterpret_cast<const int*>(w + P->off_zq_av);
+  t.zq_w = reinterpret_cast<const T*>(w + P->off_zq_w);
   return t;
 }
 
@@ -256,6 +288,8 @@ int timed(lam_plan_s* P, int slot, hipStream_t s, const char* what, F&& launch) 
   return hip_status(e, what);
 }
 
+double inv_hw(const lam_plan_s* P) { return 1.0 / ((double)P->p.h * (double)P->p.w); }
+
 // ---------------------------------------------------------------- operators
 template <typename T>
 int run_fwd(lam_plan_s* P, const void* u, bool real_in, const void* dhat, void* out, bool to_space, hipStream_t s) {
@@ -276,7 +310,7 @@ int run_fwd(lam_plan_s* P, const void* u, bool real_in, const void* dhat, void* 
   }
   if (!rc && to_space) {
     rc = timed(P, K_ROWFFT, s, "F*_2D rows", [&] { return launch_rowfft<T>(c, o, o, true, D, tb, s); });
-    if (!rc) rc = timed(P, K_COLFFT, s, "F*_2D columns", [&] { return launch_colfft<T>(c, o, o, true, D, tb, s); });
+    if (!rc) rc = timed(P, K_COLFFT, s, "F*_2D columns", [&] { return launch_colfft<T>(c, o, o, true, inv_hw(P), D, tb, s); });
   }
   return rc;
 }
@@ -294,7 +328,7 @@ int run_adj(lam_plan_s* P, const void* in, bool from_space, void* u, bool real_o
   int rc = 0;
   if (from_space) {
     rc = timed(P, K_ROWFFT, s, "F_2D rows", [&] { return launch_rowfft<T>(c, r, Pb, false, D, tb, s); });
-    if (!rc) rc = timed(P, K_COLFFT, s, "F_2D columns", [&] { return launch_colfft<T>(c, Pb, Pb, false, D, tb, s); });
+    if (!rc) rc = timed(P, K_COLFFT, s, "F_2D columns", [&] { return launch_colfft<T>(c, Pb, Pb, false, inv_hw(P), D, tb, s); });
     r = Pb;
   }
   for (int k0 = 0; !rc && k0 < P->p.h; k0 += P->slab) {
@@ -304,6 +338,17 @@ int run_adj(lam_plan_s* P, const void* in, bool from_space, void* u, bool real_o
     if (!rc) rc = timed(P, K_YCOL_ADJ, s, "F*_u2D y-FFT", [&] { return launch_ycol_adj<T>(c, Tb, U1, k0, ns, D, tb, s); });
   }
   if (!rc) rc = timed(P, K_ZADJ, s, "F*_u1D", [&] { return launch_zadj<T>(c, U1, u, real_out, D, tb, s); });
+  return rc;
+}
+
+// d^ = W d: centred forward 2D DFT per projection, unnormalised (Algorithm 2's d^)
+template <typename T>
+int run_data_hat(lam_plan_s* P, const void* d, void* dhat, hipStream_t s) {
+  const Tables<T> tb = tables<T>(P);
+  const cpx<T>* in = reinterpret_cast<const cpx<T>*>(d);
+  cpx<T>* o = reinterpret_cast<cpx<T>*>(dhat);
+  int rc = timed(P, K_ROWFFT, s, "W rows", [&] { return launch_rowfft<T>(P->cfg, in, o, false, P->D, tb, s); });
+  if (!rc) rc = timed(P, K_COLFFT, s, "W columns", [&] { return launch_colfft<T>(P->cfg, o, o, false, 1.0, P->D, tb, s); });
   return rc;
 }
 
@@ -396,10 +441,12 @@ int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes) {
   blobs.emplace_back(p->off_cth, pack<double>(p->cth));
   blobs.emplace_back(p->off_sth, pack<double>(p->sth));
   blobs.emplace_back(p->off_rc, pack<double>(p->rc));
-  {
-    std::vector<unsigned char> zb(p->zbase.size() * sizeof(int));
-    std::memcpy(zb.data(), p->zbase.data(), zb.size());
-    blobs.emplace_back(p->off_zbase, std::move(zb));
+  blobs.emplace_back(p->off_zq_w, f ? pack<float>(p->zq_w) : pack<double>(p->zq_w));
+  for (auto pr : {std::make_pair(p->off_zbase, &p->zbase), std::make_pair(p->off_zq_ptr, &p->zq_ptr),
+                  std::make_pair(p->off_zq_av, &p->zq_av)}) {
+    std::vector<unsigned char> b(pr.second->size() * sizeof(int));
+    std::memcpy(b.data(), pr.second->data(), b.size());
+    blobs.emplace_back(pr.first, std::move(b));
   }
   for (auto& b : blobs) {
     const hipError_t e = hipMemcpy(w + b.first, b.second.data(), b.second.size(), hipMemcpyHostToDevice);
@@ -419,6 +466,15 @@ int lam_fwd_hat(lam_plan p, const void* u, const void* dhat, void* r, void* s) {
   return fwd_any(p, u, false, dhat, r, false, s);
 }
 int lam_adj_hat(lam_plan p, const void* r, void* u, void* s) { g_last_error.clear(); return adj_any(p, r, false, u, false, s); }
+
+int lam_data_hat(lam_plan p, const void* d, void* dhat, void* stream) {
+  g_last_error.clear();
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!d || !dhat) return fail(LAM_ERR_ARG, "null array pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return p->p.dtype == LAM_C64 ? run_data_hat<float>(p, d, dhat, s) : run_data_hat<double>(p, d, dhat, s);
+}
 
 int lam_profile(lam_plan p, int on) {
   if (!p) return fail(LAM_ERR_ARG, "null plan");

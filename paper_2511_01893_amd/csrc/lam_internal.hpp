@@ -27,6 +27,9 @@ struct Tables {
   const double* cth;  // [ntheta] cos(theta)
   const double* sth;  // [ntheta] sin(theta)
   const double* rc;   // [2m] exp(-beta (2 o + 1)), o = -m+1 ..
+  const int* zq_ptr;  // [M0 + 1] inverse z table: for grid point q, entries zq_ptr[q] .. zq_ptr[q+1]
+  const int* zq_av;   // [h 2m] k_v index of each entry
+  const T* zq_w;      // [h 2m] weight of each entry
 };
 
 // Launch shapes chosen by the host plan.
@@ -35,7 +38,7 @@ struct LaunchCfg {
   int y_log2TX, y_threads; size_t y_lds;    // y-FFT column blocks
   int x_log2RB, x_threads; size_t x_lds;    // x-FFT row blocks
   int g_log2TS, g_threads; size_t g_lds;    // gather tiles
-  size_t s_lds;                             // scatter tiles
+  int s_threads; size_t s_lds;              // scatter tiles
   int r_log2RB, r_threads; size_t r_lds;    // 2D FFT row pass
   int c_log2TX, c_threads; size_t c_lds;    // 2D FFT column pass
 };
@@ -68,7 +71,7 @@ template <typename T>
 hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
                          const Tables<T>& tb, hipStream_t s);
 template <typename T>
-hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
-                         const Tables<T>& tb, hipStream_t s);
+hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale,
+                         const Dims& D, const Tables<T>& tb, hipStream_t s);
 
 }  // namespace lam

@@ -66,8 +66,12 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   }
 }
 
-// F*_u1D: spread the h samples of each column into an LDS line of M0
-// (LDS float atomics), inverse FFT (as conj-FFT-conj), crop, deconvolve.
+// F*_u1D: the transpose of the z gather, evaluated as a gather through the
+// inverse table (for every grid point q of the oversampled line, the (k_v,
+// weight) pairs whose stencil covers q), so no atomics are needed: stage the
+// h samples of TX columns in LDS, form each grid value in registers, write
+// the grid over the staging area, inverse FFT (conj-FFT-conj), crop,
+// deconvolve.
 template <typename T, int MH, bool REAL_OUT>
 __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, void* __restrict__ uout, Dims D,
                                                Tables<T> tb, int log2TX) {
@@ -76,30 +80,44 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
   const int x0 = blockIdx.x * TX, y = blockIdx.y;
   const int tid = threadIdx.x, nth = blockDim.x;
   const size_t plane = (size_t)D.n1 * D.n2;
-  const cpx<T> zero = mk((T)0, (T)0);
-  for (int e = tid; e < M0 * TX; e += nth) buf[e] = zero;
-  __syncthreads();
   for (int e = tid; e < D.h * TX; e += nth) {
     const int av = e >> log2TX, b = e & (TX - 1);
-    const cpx<T> v = u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b];
-    const int base = tb.zbase[av] - MH + 1;
-    const T* w = tb.zw + av * 2 * MH;
+    buf[e] = conj(u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b]);
+  }
+  __syncthreads();
+  cpx<T> v[VPT];
+  const int total = M0 * TX;
 #pragma unroll
-    for (int i = 0; i < 2 * MH; ++i) {
-      T* cell = reinterpret_cast<T*>(&buf[((base + i) & (M0 - 1)) * TX + b]);
-      atomicAdd(cell, w[i] * v.x);
-      atomicAdd(cell + 1, -w[i] * v.y);          // accumulate conj(v): inverse FFT via conj
+  for (int it = 0; it < VPT; ++it) {
+    const int e = tid + it * nth;
+    T ax = 0, ay = 0;
+    if (e < total) {
+      const int q = e >> log2TX, b = e & (TX - 1);
+      const int beg = tb.zq_ptr[q], end = tb.zq_ptr[q + 1];
+      for (int j = beg; j < end; ++j) {
+        const T w = tb.zq_w[j];
+        const cpx<T> g = buf[tb.zq_av[j] * TX + b];
+        ax += w * g.x;
+        ay += w * g.y;
+      }
     }
+    v[it] = mk(ax, ay);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < VPT; ++it) {
+    const int e = tid + it * nth;
+    if (e < total) buf[e] = v[it];
   }
   __syncthreads();
   lds_fft<T, VPT>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw);
   for (int e = tid; e < n0 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
-    const cpx<T> v = buf[((a - n0 / 2) & (M0 - 1)) * TX + b];
+    const cpx<T> g = buf[((a - n0 / 2) & (M0 - 1)) * TX + b];
     const T c = tb.cz[a];
     const size_t gi = (size_t)a * plane + (size_t)y * D.n2 + x0 + b;
-    if constexpr (REAL_OUT) reinterpret_cast<T*>(uout)[gi] = v.x * c;
-    else reinterpret_cast<cpx<T>*>(uout)[gi] = mk(v.x * c, -v.y * c);
+    if constexpr (REAL_OUT) reinterpret_cast<T*>(uout)[gi] = g.x * c;
+    else reinterpret_cast<cpx<T>*>(uout)[gi] = mk(g.x * c, -g.y * c);
   }
 }
 
@@ -348,24 +366,32 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
 }
 
 // ---------------------------------------------------------------------------
-// F*_u2D scatter into one tile of the oversampled grid (owner computes)
+// F*_u2D scatter into one tile of the oversampled grid (owner computes).
+//
+// One lane per candidate target: FP64 coordinates and weights, then the 2m x
+// 2m taps that land in the tile are added into an FP64 LDS accumulator with
+// native ds_add_f64 (gfx950 executes FP64 LDS atomics at close to the rate
+// of plain stores, unlike FP32 LDS atomics).  Accumulating in FP64 also
+// makes the sum insensitive to the arrival order.  Every cell of the tile is
+// finally rounded to T and written once to the grid, so G needs no clearing
+// and no global atomics.
 // ---------------------------------------------------------------------------
 template <typename T, int MH>
 __global__ __launch_bounds__(256) void k_scatter(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ Gb, int k0,
                                                  Dims D, Tables<T> tb, int log2TS) {
+  constexpr int W = 2 * MH;
   const int TS = 1 << log2TS, PA = TS + 1;
   const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
   const int nt = D.ntheta;
-  cpx<T>* acc = reinterpret_cast<cpx<T>*>(lam_smem);
-  int* scan = reinterpret_cast<int*>(acc + TS * PA);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double* acc = reinterpret_cast<double*>(lam_smem);          // [TS][PA] complex as (re, im) doubles
+  int* scan = reinterpret_cast<int*>(acc + 2 * TS * PA);
   int* lo = scan + nt + 1;
   int* part = lo + nt;
   const int kk = blockIdx.z, k = k0 + kk;
   const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int LX = TS + 2 * MH - 1;
-  const cpx<T> zero = mk((T)0, (T)0);
-  for (int e = tid; e < TS * PA; e += nth) acc[e] = zero;
+  const int LX = TS + W - 1;
+  for (int e = tid; e < 2 * TS * PA; e += nth) acc[e] = 0.0;
   for (int t = tid; t < nt; t += nth) {
     int l, h;
     cand_range(D.xy, tb.cth[t], tb.sth[t], k, x0 - MH, LX, M2, y0 - MH, LX, M1, l, h);
@@ -378,28 +404,30 @@ __global__ __launch_bounds__(256) void k_scatter(const cpx<T>* __restrict__ in, 
   for (int i = tid; i < total; i += nth) {
     const int t = find_theta(scan, nt, i);
     const int aku = lo[t] + (i - scan[t]);
-    const double ct = tb.cth[t], st = tb.sth[t];
     double sx, sy;
-    target_coords(D.xy, ct, st, k, aku, sx, sy);
-    const int fx = (int)floor(sx), fy = (int)floor(sy);
-    if (((fx - (x0 - MH)) & (M2 - 1)) >= LX || ((fy - (y0 - MH)) & (M1 - 1)) >= LX) continue;
-    T wx[2 * MH], wy[2 * MH];
+    target_coords(D.xy, tb.cth[t], tb.sth[t], k, aku, sx, sy);
+    // stencil corner relative to the tile, modulo the grid; the stencil
+    // touches the tile if it starts inside it or wraps into it
+    const int rx0 = ((int)floor(sx) - MH + 1 - x0) & (M2 - 1);
+    const int ry0 = ((int)floor(sy) - MH + 1 - y0) & (M1 - 1);
+    if (!((rx0 < TS || rx0 > M2 - W) && (ry0 < TS || ry0 > M1 - W))) continue;
+    T wx[W], wy[W];
     int bx, by;
     stencil_weights<T, MH>(sx, D.beta, tb.rc, bx, wx);
     stencil_weights<T, MH>(sy, D.beta, tb.rc, by, wy);
     const cpx<T> v = in[((size_t)t * D.h + k) * D.w + aku];
 #pragma unroll
-    for (int iy = 0; iy < 2 * MH; ++iy) {
-      const int ry = (by - MH + 1 + iy - y0) & (M1 - 1);
-      if (ry >= TS) continue;
-      const T vx = wy[iy] * v.x, vy = wy[iy] * v.y;
+    for (int iy = 0; iy < W; ++iy) {
+      const int row = (ry0 + iy) & (M1 - 1);
+      if (row >= TS) continue;
+      const double vx = (double)(wy[iy] * v.x), vy = (double)(wy[iy] * v.y);
 #pragma unroll
-      for (int ix = 0; ix < 2 * MH; ++ix) {
-        const int rx = (bx - MH + 1 + ix - x0) & (M2 - 1);
-        if (rx >= TS) continue;
-        T* cell = reinterpret_cast<T*>(&acc[ry * PA + rx]);
-        atomicAdd(cell, wx[ix] * vx);
-        atomicAdd(cell + 1, wx[ix] * vy);
+      for (int ix = 0; ix < W; ++ix) {
+        const int col = (rx0 + ix) & (M2 - 1);
+        if (col >= TS) continue;
+        double* cell = acc + 2 * (row * PA + col);
+        atomicAdd(cell, (double)wx[ix] * vx);
+        atomicAdd(cell + 1, (double)wx[ix] * vy);
       }
     }
   }
@@ -407,7 +435,8 @@ __global__ __launch_bounds__(256) void k_scatter(const cpx<T>* __restrict__ in, 
   cpx<T>* G = Gb + (size_t)kk * M1 * M2;
   for (int e = tid; e < TS * TS; e += nth) {
     const int r = e >> log2TS, c = e & (TS - 1);
-    G[(size_t)(y0 + r) * M2 + x0 + c] = acc[r * PA + c];
+    const double* cell = acc + 2 * (r * PA + c);
+    G[(size_t)(y0 + r) * M2 + x0 + c] = mk((T)cell[0], (T)cell[1]);
   }
 }
 
@@ -567,7 +596,7 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
     auto k = k_scatter<T, MH>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
     dim3 grid((1 << D.log2M2) >> c.g_log2TS, (1 << D.log2M1) >> c.g_log2TS, ns);
-    hipLaunchKernelGGL(k, grid, dim3(c.g_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
+    hipLaunchKernelGGL(k, grid, dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
   });
   return hipGetLastError();
 }
@@ -608,13 +637,13 @@ hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool
 }
 
 template <typename T>
-hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
-                         const Tables<T>& tb, hipStream_t s) {
+hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale_d,
+                         const Dims& D, const Tables<T>& tb, hipStream_t s) {
   const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
   auto k = k_colfft<T>;
   hipError_t e = prep(k, c.c_lds);
   if (e != hipSuccess) return e;
-  const T scale = (T)(1.0 / ((double)D.h * (double)D.w));
+  const T scale = (T)scale_d;
   hipLaunchKernelGGL(k, dim3(D.w >> c.c_log2TX, D.ntheta), dim3(c.c_threads), c.c_lds, s, in, out, log2h, log2w,
                      c.c_log2TX, inverse ? 1 : 0, scale, tb);
   return hipGetLastError();
@@ -639,7 +668,7 @@ hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool
                                          const Tables<T>&, hipStream_t);                                         \
   template hipError_t launch_rowfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, const Dims&,              \
                                        const Tables<T>&, hipStream_t);                                           \
-  template hipError_t launch_colfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, const Dims&,              \
+  template hipError_t launch_colfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, double, const Dims&,      \
                                        const Tables<T>&, hipStream_t);
 
 LAM_INST(float)

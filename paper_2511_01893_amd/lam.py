@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         for name in ("lam_fwd", "lam_adj", "lam_fwd_real", "lam_adj_real", "lam_adj_hat"):
             getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_fwd_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.lam_data_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_admm_work_bytes.argtypes = [c_void_p]
         L.lam_admm_work_bytes.restype = c_size_t
         L.lam_admm_step.argtypes = [c_void_p, POINTER(AdmmState), c_void_p, c_int, c_void_p]
@@ -191,6 +192,13 @@ class Plan:
         return out
 
 
+    def data_hat(self, d: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """d^ = W d: unnormalised centred 2D DFT of every projection (Algorithm 2's d^)."""
+        self._arr(d, self.data_shape, "d")
+        out = torch.empty(self.data_shape, dtype=self.dtype, device=self.device) if out is None else out
+        _check(lib().lam_data_hat(self._h, c_void_p(d.data_ptr()), c_void_p(out.data_ptr()), self._stream()))
+        return out
+
     # ---------------------------------------------------------------- timing
     def profile(self, on: bool = True):
         """Bracket every kernel of this plan with HIP events (for measurement)."""
@@ -223,6 +231,52 @@ class LamOp(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         return ctx.plan.adj(g.contiguous(), real=ctx.real), None
+
+
+class AdmmTV:
+    """ADMM-TV state on the device for min_u 1/2 |L u - d|^2 + alpha |u|_TV (Equation 1).
+
+    u (real), psi and lam (3 x volume) start at zero; rho starts at rho0.
+    step() runs one ADMM iteration (LSP with n_inner CG steps, RSP, multiplier
+    and penalty updates) entirely in liblam.so's kernels."""
+
+    def __init__(self, plan: Plan, alpha: float, rho0: float = 0.5):
+        self.plan = plan
+        dev, rdt = plan.device, plan.rdtype
+        self.u = torch.zeros(plan.vol_shape, dtype=rdt, device=dev)
+        self.psi = torch.zeros((3,) + plan.vol_shape, dtype=rdt, device=dev)
+        self.lam = torch.zeros((3,) + plan.vol_shape, dtype=rdt, device=dev)
+        self.work = torch.empty(lib().lam_admm_work_bytes(plan._h), dtype=torch.uint8, device=dev)
+        self.scal = torch.zeros(8, dtype=torch.float64, device=dev)
+        self.scal[0] = rho0
+        self.scal[1] = alpha
+
+    @property
+    def rho(self) -> float:
+        return float(self.scal[0].item())
+
+    def diagnostics(self) -> dict:
+        s = self.scal.tolist()
+        return {"rho": s[0], "alpha": s[1], "gamma": s[2], "primal": s[3], "dual": s[4], "grad_norm": s[5],
+                "rho_used": s[6]}
+
+    def step(self, dhat: torch.Tensor, n_inner: int = 4):
+        self.plan._arr(dhat, self.plan.data_shape, "dhat")
+        st = AdmmState(c_void_p(self.u.data_ptr()), c_void_p(self.psi.data_ptr()), c_void_p(self.lam.data_ptr()),
+                       c_void_p(self.work.data_ptr()),
+                       ctypes.cast(c_void_p(self.scal.data_ptr()), POINTER(c_double)))
+        _check(lib().lam_admm_step(self.plan._h, byref(st), c_void_p(dhat.data_ptr()), n_inner,
+                                   self.plan._stream()))
+
+
+def admm_tv(plan: Plan, d: torch.Tensor, alpha: float, n_outer: int = 4, n_inner: int = 4,
+            rho0: float = 0.5) -> AdmmTV:
+    """Run n_outer ADMM-TV iterations on projections d (complex, (ntheta, h, w))."""
+    dhat = plan.data_hat(d)
+    s = AdmmTV(plan, alpha, rho0)
+    for _ in range(n_outer):
+        s.step(dhat, n_inner)
+    return s
 
 
 def plan_for(name: str, dtype=torch.complex64, device="cuda", slab: int = 0) -> Plan:
