@@ -73,7 +73,7 @@ typedef enum {
  * angles, detector h x w; plus tilt, oversampling and kernel half-width). */
 typedef struct {
   int n0, n1, n2;        /* volume (z, y, x); powers of two, 16 .. 4096            */
-  int ntheta;            /* number of projection angles, >= 1                       */
+  int ntheta;            /* number of projection angles, 1 .. 4096                  */
   const double* theta;   /* host array [ntheta] in radians, or NULL: 2 pi t/ntheta  */
   double phi;            /* tilt of the rotation axis from the tomographic
                             position, radians, 0 <= phi < pi/2 (phi = 0: tomography) */

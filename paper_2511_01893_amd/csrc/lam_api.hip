@@ -32,7 +32,8 @@ int ilog2(long v) { int r = 0; while ((1L << r) < v) ++r; return r; }
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr int kVPT = 16;
+// complex values per thread per FFT stage (as the kernels are built): 16 for complex64, 8 for complex128
+int vpt_of(size_t csize) { return csize == 8 ? 16 : 8; }
 
 }  // namespace
 
@@ -43,14 +44,15 @@ struct lam_plan_s {
   double beta = 0;
   size_t csize = 8, rsize = 4;
   // host tables (FP64)
-  std::vector<double> tw, cz, cy, cx, zw, cth, sth, rc;
+  std::vector<double> tw, cz, cy, cx, zw, cth, sth, rc, line;
   std::vector<int> zbase, zq_ptr, zq_av;
   std::vector<double> zq_w;
   // workspace layout (byte offsets)
   size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zw = 0, off_cth = 0, off_sth = 0,
-         off_rc = 0, off_zq_ptr = 0, off_zq_av = 0, off_zq_w = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
+         off_rc = 0, off_line = 0, off_zq_ptr = 0, off_zq_av = 0, off_zq_w = 0, off_tlist = 0, off_toff = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
+  int ntx = 1, nty = 1;        // tiles of the oversampled grid per slice
   Dims D{};
   LaunchCfg cfg{};
   // optional per-kernel timing (lam_profile)
@@ -80,18 +82,23 @@ std::vector<double> deconv(int n, int R, int m) {
 void col_cfg(int log2N, int ncols, size_t csize, int& log2TX, int& threads, size_t& lds) {
   const long N = 1L << log2N;
   int TX = 16;
-  while (TX > 1 && (TX > ncols || N * TX * (long)csize > 131072 || N * TX / kVPT > 1024)) TX >>= 1;
+  const int vp = vpt_of(csize);
+  while (TX > 1 && (TX > ncols || N * TX * (long)csize > 131072 || N * TX / vp > 1024)) TX >>= 1;
   log2TX = ilog2(TX);
-  threads = (int)std::max<long>(64, N * TX / kVPT);
+  threads = (int)std::max<long>(64, N * TX / vp);
   lds = (size_t)N * TX * csize;
 }
 
 void row_cfg(int log2N, long nrows, size_t csize, int& log2RB, int& threads, size_t& lds) {
   const long N = 1L << log2N;
   int RB = 16;
-  while (RB > 1 && (RB > nrows || N * RB * (long)csize > 131072 || N * RB / kVPT > 1024 || nrows % RB)) RB >>= 1;
+  // rows are contiguous in memory, so small row blocks stay coalesced: cap LDS at 32 KB so that
+  // several work-groups share a CU and one's loads overlap another's FFT (the row kernels are
+  // at most 1024 threads)
+  const int vp = vpt_of(csize);
+  while (RB > 1 && (RB > nrows || N * RB * (long)csize > 32768 || N * RB / vp > 1024 || nrows % RB)) RB >>= 1;
   log2RB = ilog2(RB);
-  threads = (int)std::max<long>(64, N * RB / kVPT);
+  threads = (int)std::max<long>(64, N * RB / vp);
   lds = (size_t)N * RB * csize;
 }
 
@@ -149,6 +156,16 @@ int build(lam_plan_s* P) {
     P->cth[t] = std::cos(P->theta[t]);
     P->sth[t] = std::sin(P->theta[t]);
   }
+  // per-angle line parameters of the 2D targets: s_x = A_x k_u + C_x (k_v/h), s_y = A_y k_u + C_y (k_v/h),
+  // k_u, k_v centred integers; used only to bound the candidate k_u range of a tile
+  P->line.assign(6 * (size_t)p.ntheta, 0.0);
+  for (int t = 0; t < p.ntheta; ++t) {
+    const double sphi = std::sin(p.phi);
+    const double Ax = R * (double)p.n2 * P->cth[t] / p.w, Ay = R * (double)p.n1 * P->sth[t] / p.w;
+    double* l = &P->line[6 * (size_t)t];
+    l[0] = Ax; l[1] = std::fabs(Ax) < 1e-8 ? 0.0 : 1.0 / Ax; l[2] = R * (double)p.n2 * sphi * P->sth[t];
+    l[3] = Ay; l[4] = std::fabs(Ay) < 1e-8 ? 0.0 : 1.0 / Ay; l[5] = -R * (double)p.n1 * sphi * P->cth[t];
+  }
   P->rc.assign(16, 0.0);
   for (int i = 0; i < 2 * m - 1; ++i) {
     const double o = (double)(i - m + 1);
@@ -175,9 +192,16 @@ int build(lam_plan_s* P) {
   P->off_cth = take((size_t)p.ntheta * sizeof(double));
   P->off_sth = take((size_t)p.ntheta * sizeof(double));
   P->off_rc = take(16 * sizeof(double));
+  P->off_line = take(6 * (size_t)p.ntheta * sizeof(double));
   P->off_zq_ptr = take(((size_t)P->M0 + 1) * sizeof(int));
   P->off_zq_av = take((size_t)p.h * 2 * m * sizeof(int));
   P->off_zq_w = take((size_t)p.h * 2 * m * P->rsize);
+  // per-slice target lists of the tiles (built on the device by lam_set_workspace)
+  const int TS = std::min(64, std::min(P->M1, P->M2));
+  P->ntx = P->M2 / TS;
+  P->nty = P->M1 / TS;
+  P->off_tlist = take((size_t)p.h * p.ntheta * p.w * sizeof(int));
+  P->off_toff = take((size_t)p.h * ((size_t)P->ntx * P->nty * 9 + 1) * sizeof(int));
   P->off_u1 = take((size_t)p.h * p.n1 * p.n2 * P->csize);
   P->off_p = take((size_t)p.ntheta * p.h * p.w * P->csize);
   P->off_t = take((size_t)S * P->M1 * p.n2 * P->csize);
@@ -201,23 +225,26 @@ int build(lam_plan_s* P) {
   // the z adjoint stages h samples per column in the same LDS: shrink the tile if h > M0
   while (c.z_log2TX > 0 && (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize > 131072) {
     --c.z_log2TX;
-    c.z_threads = (int)std::max<long>(64, ((long)P->M0 << c.z_log2TX) / kVPT);
+    c.z_threads = (int)std::max<long>(64, ((long)P->M0 << c.z_log2TX) / vpt_of(P->csize));
   }
   c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize;
   col_cfg(D.log2M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
   row_cfg(D.log2M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
   row_cfg(ilog2(p.w), p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
   col_cfg(ilog2(p.h), p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
-  const int TS = std::min(64, std::min(P->M1, P->M2));
   c.g_log2TS = ilog2(TS);
-  c.g_threads = 256;
-  const size_t ints = (2 * (size_t)p.ntheta + 1 + 2 * 256) * sizeof(int);
+  // gather: the tile plus its (2m-1) halo; scatter: two FP64 planes of the tile (pitch TS + 8)
+  // plus one record of 2 (2m) + 2 values of T and a corner per thread
   const size_t Pt = TS + 2 * m - 1;
-  c.g_lds = align_up(Pt * Pt * P->csize, 16) + ints;
-  // scatter: FP64 accumulator tile + candidate scan
-  c.s_threads = 256;
-  c.s_lds = (size_t)TS * (TS + 1) * 16 + (2 * (size_t)p.ntheta + 1 + 2 * 256) * sizeof(int);
-  if (c.g_lds > kLdsMax || c.s_lds > kLdsMax) return fail(LAM_ERR_ARG, "ntheta too large for the tile kernels' LDS");
+  c.g_threads = 256;
+  c.g_lds = (Pt * Pt + (Pt * Pt & 1)) * P->csize;
+  const size_t planes = 2 * (size_t)TS * (TS + 8) * sizeof(double);
+  const size_t RS = 2 * 2 * (size_t)m + 2;
+  auto s_bytes = [&](size_t nthr) { return planes + nthr * RS * P->rsize + nthr * sizeof(int) + 28 * sizeof(int); };
+  c.s_threads = 1024;
+  while (c.s_threads > 64 && s_bytes(c.s_threads) > kLdsMax) c.s_threads /= 2;
+  c.s_lds = s_bytes(c.s_threads);
+  if (c.g_lds > kLdsMax || c.s_lds > kLdsMax) return fail(LAM_ERR_ARG, "tile kernels do not fit the LDS");
   return LAM_OK;
 }
 
@@ -235,6 +262,9 @@ Tables<T> tables(const lam_plan_s* P) {
   t.cth = reinterpret_cast<const double*>(w + P->off_cth);
   t.sth = reinterpret_cast<const double*>(w + P->off_sth);
   t.rc = reinterpret_cast<const double*>(w + P->off_rc);
+  t.line = reinterpret_cast<const double*>(w + P->off_line);
+  t.tlist = reinterpret_cast<const int*>(w + P->off_tlist);
+  t.toff = reinterpret_cast<const int*>(w + P->off_toff);
   t.zq_ptr = reinterpret_cast<const int*>(w + P->off_zq_ptr);
   t.zq_av = reinterpret_cast<const int*>(w + P->off_zq_av);
   t.zq_w = reinterpret_cast<const T*>(w + P->off_zq_w);
@@ -248,6 +278,13 @@ std::vector<unsigned char> pack(const std::vector<double>& v) {
   for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
   return out;
 }
+
+// Sort every slice's targets into per-tile lists on the device (once per
+// workspace): count per (slice, tile, border class), exclusive scan on the
+// host with the invariant that each slice lists exactly n_theta w targets,
+// then fill.  Runs on the null stream and waits for it.
+template <typename T>
+int build_lists(lam_plan_s* P);
 
 int hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return LAM_OK;
@@ -289,6 +326,42 @@ int timed(lam_plan_s* P, int slot, hipStream_t s, const char* what, F&& launch) 
 }
 
 double inv_hw(const lam_plan_s* P) { return 1.0 / ((double)P->p.h * (double)P->p.w); }
+
+template <typename T>
+int build_lists(lam_plan_s* P) {
+  const Tables<T> tb = tables<T>(P);
+  int* toff = reinterpret_cast<int*>(P->ws + P->off_toff);
+  int* tlist = reinterpret_cast<int*>(P->ws + P->off_tlist);
+  const size_t per_slice = (size_t)P->ntx * P->nty * 9 + 1;
+  const int h = P->p.h;
+  const int chunk = 256;   // slices per launch
+  for (int k0 = 0; k0 < h; k0 += chunk) {
+    const int rc = hip_status(launch_list_count<T>(P->cfg, k0, std::min(chunk, h - k0), P->D, tb, toff, nullptr),
+                              "target count");
+    if (rc) return rc;
+  }
+  std::vector<int> cnt((size_t)h * per_slice);
+  hipError_t e = hipMemcpy(cnt.data(), toff, cnt.size() * sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(e, "target count copy");
+  const long expect = (long)P->p.ntheta * P->p.w;
+  for (int k = 0; k < h; ++k) {
+    int* c = &cnt[(size_t)k * per_slice];
+    long run = 0;
+    for (size_t i = 0; i + 1 < per_slice; ++i) { const int v = c[i]; c[i] = (int)run; run += v; }
+    c[per_slice - 1] = (int)run;
+    if (run != expect)
+      return fail(LAM_ERR_STATE, "target lists: slice " + std::to_string(k) + " holds " + std::to_string(run) +
+                                     " targets, expected " + std::to_string(expect));
+  }
+  e = hipMemcpy(toff, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_status(e, "target offset copy");
+  for (int k0 = 0; k0 < h; k0 += chunk) {
+    const int rc = hip_status(launch_list_fill<T>(P->cfg, k0, std::min(chunk, h - k0), P->D, tb, toff, tlist, nullptr),
+                              "target fill");
+    if (rc) return rc;
+  }
+  return hip_status(hipDeviceSynchronize(), "target list build");
+}
 
 // ---------------------------------------------------------------- operators
 template <typename T>
@@ -396,7 +469,7 @@ int lam_init(lam_plan* out, const lam_params* p) {
     bad = "n0, n1, n2 must be powers of two in [16, 4096]";
   else if (!is_pow2_in(p->h, 16, 4096) || !is_pow2_in(p->w, 16, 4096))
     bad = "h, w must be powers of two in [16, 4096]";
-  else if (p->ntheta < 1 || p->ntheta > 8192) bad = "ntheta must be in [1, 8192]";
+  else if (p->ntheta < 1 || p->ntheta > 4096) bad = "ntheta must be in [1, 4096]";
   else if (!(p->phi >= 0.0 && p->phi < M_PI / 2)) bad = "phi must be in [0, pi/2)";
   else if (p->oversample != 2) bad = "oversample must be 2";
   else if (p->m < 1 || p->m > 8) bad = "m must be in [1, 8]";
@@ -441,6 +514,7 @@ int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes) {
   blobs.emplace_back(p->off_cth, pack<double>(p->cth));
   blobs.emplace_back(p->off_sth, pack<double>(p->sth));
   blobs.emplace_back(p->off_rc, pack<double>(p->rc));
+  blobs.emplace_back(p->off_line, pack<double>(p->line));
   blobs.emplace_back(p->off_zq_w, f ? pack<float>(p->zq_w) : pack<double>(p->zq_w));
   for (auto pr : {std::make_pair(p->off_zbase, &p->zbase), std::make_pair(p->off_zq_ptr, &p->zq_ptr),
                   std::make_pair(p->off_zq_av, &p->zq_av)}) {
@@ -452,8 +526,14 @@ int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes) {
     const hipError_t e = hipMemcpy(w + b.first, b.second.data(), b.second.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(LAM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e));
   }
+  unsigned char* old_ws = p->ws;
   p->ws = w;
   p->ws_bytes = bytes;
+  const int rc = p->p.dtype == LAM_C64 ? build_lists<float>(p) : build_lists<double>(p);
+  if (rc) {
+    p->ws = old_ws;
+    return rc;
+  }
   return LAM_OK;
 }
 

@@ -11,6 +11,10 @@ struct alignas(2 * sizeof(T)) cpx {
   T x, y;
 };
 
+// complex values per thread per FFT stage (and per batched load): 16 for
+// complex64, 8 for complex128, so the register arrays stay in VGPRs
+template <typename T> constexpr int vpt() { return sizeof(T) == 4 ? 16 : 8; }
+
 template <typename T> __device__ __forceinline__ cpx<T> mk(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
 template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
 template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }

@@ -27,9 +27,12 @@ struct Tables {
   const double* cth;  // [ntheta] cos(theta)
   const double* sth;  // [ntheta] sin(theta)
   const double* rc;   // [2m] exp(-beta (2 o + 1)), o = -m+1 ..
+  const double* line; // [ntheta][6] per angle: A_x, 1/A_x, C_x, A_y, 1/A_y, C_y (s = A k_u + C k_v/h-units, 1/A = 0 if |A| < 1e-8)
   const int* zq_ptr;  // [M0 + 1] inverse z table: for grid point q, entries zq_ptr[q] .. zq_ptr[q+1]
   const int* zq_av;   // [h 2m] k_v index of each entry
   const T* zq_w;      // [h 2m] weight of each entry
+  const int* tlist;   // per slice [n_theta w]: targets sorted by (tile, border class), t * 4096 + k_u index
+  const int* toff;    // per slice [n_tiles 9 + 1]: offsets of the (tile, class) lists within the slice
 };
 
 // Launch shapes chosen by the host plan.
@@ -37,7 +40,7 @@ struct LaunchCfg {
   int z_log2TX, z_threads; size_t z_lds;    // F_u1D column blocks
   int y_log2TX, y_threads; size_t y_lds;    // y-FFT column blocks
   int x_log2RB, x_threads; size_t x_lds;    // x-FFT row blocks
-  int g_log2TS, g_threads; size_t g_lds;    // gather tiles
+  int g_log2TS, g_threads; size_t g_lds;    // gather tiles (TS = 2^g_log2TS, also the scatter's)
   int s_threads; size_t s_lds;              // scatter tiles
   int r_log2RB, r_threads; size_t r_lds;    // 2D FFT row pass
   int c_log2TX, c_threads; size_t c_lds;    // 2D FFT column pass
@@ -67,6 +70,12 @@ hipError_t launch_xrow_adj(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* Tb, int
 template <typename T>
 hipError_t launch_ycol_adj(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* u1, int k0, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s);
+template <typename T>
+hipError_t launch_list_count(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, int* counts,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, const int* offs,
+                            int* lists, hipStream_t s);
 template <typename T>
 hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
                          const Tables<T>& tb, hipStream_t s);

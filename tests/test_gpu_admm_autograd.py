@@ -66,9 +66,12 @@ def test_autograd_gradient_matches_oracle(L, dtype, tol):
 def test_autograd_gradcheck_c128(L):
     plan, geo = make(L, torch.complex128, 16, 8, 25.0)
     u = torch.from_numpy(I.random_complex(geo.vol_shape, 2).real).cuda().requires_grad_(True)
-    assert torch.autograd.gradcheck(lambda x: L.LamOp.apply(x, plan), (u,), fast_mode=True, atol=1e-8, rtol=1e-6)
+    # the adjoint's tile accumulation (FP64 LDS atomics) is order-independent only to rounding,
+    # so repeated backward passes may differ in the last bits
+    kw = dict(fast_mode=True, atol=1e-8, rtol=1e-6, nondet_tol=1e-12)
+    assert torch.autograd.gradcheck(lambda x: L.LamOp.apply(x, plan), (u,), **kw)
     uc = torch.from_numpy(I.random_complex(geo.vol_shape, 3)).cuda().requires_grad_(True)
-    assert torch.autograd.gradcheck(lambda x: L.LamOp.apply(x, plan), (uc,), fast_mode=True, atol=1e-8, rtol=1e-6)
+    assert torch.autograd.gradcheck(lambda x: L.LamOp.apply(x, plan), (uc,), **kw)
 
 
 def test_autograd_finite_differences_c64(L):
