@@ -129,6 +129,23 @@ int lam_fwd_hat(lam_plan p, const void* u, const void* dhat, void* r, void* hip_
  * r: complex (ntheta, h, w), read only; u: complex volume. */
 int lam_adj_hat(lam_plan p, const void* r, void* u, void* hip_stream);
 
+/* Host-streamed forward and adjoint for volumes and data that live in host
+ * memory (the chunk pipeline the Background section describes for LSP, where
+ * host-to-device chunk transfers overlap the FFT work).  u_host: pinned host array (n0, n1, n2), real (u_real != 0,
+ * float/double per dtype) or complex; d_host: pinned host complex
+ * (ntheta, h, w).  The volume moves in y-slabs through two staging buffers of
+ * the workspace (F_u1D needs whole z columns), the data in theta-slabs through
+ * the workspace's resident data buffer (F_2D needs whole projections); the
+ * intermediate stage arrays stay in device memory.  Copies run on a stream the
+ * plan owns, ordered against the caller's stream with events; the call
+ * returns at once and the caller's stream is complete when the host arrays are.
+ * lam_stream_slabs sets the slab sizes (volume rows per y-slab, at most the
+ * staging capacity chosen at lam_init, about 64 MiB; projections per
+ * theta-slab). */
+int lam_fwd_streamed(lam_plan p, const void* u_host, int u_real, void* d_host, void* hip_stream);
+int lam_adj_streamed(lam_plan p, const void* d_host, void* u_host, int u_real, void* hip_stream);
+int lam_stream_slabs(lam_plan p, int y_rows, int theta_proj);
+
 /* dhat = W d: the unnormalised centred 2D DFT of every projection, computed
  * once before the LSP loop (Algorithm 2, "d^ <- F_2D d"); with this scaling
  * |L u - d|^2 = |L^ u - d^|^2 / (h w).  d, dhat: complex (ntheta, h, w);

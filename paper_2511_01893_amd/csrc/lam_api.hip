@@ -53,6 +53,11 @@ struct lam_plan_s {
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   int ntx = 1, nty = 1;        // tiles of the oversampled grid per slice
+  // host streaming (lam_fwd_streamed / lam_adj_streamed)
+  int ys = 1, ts = 1;          // volume rows per y-slab, projections per theta-slab
+  size_t off_stage = 0, stage_bytes = 0;   // two staging buffers for y-slabs
+  hipStream_t copy = nullptr;
+  hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_freed[2] = {nullptr, nullptr}, ev_start = nullptr, ev_done = nullptr;
   Dims D{};
   LaunchCfg cfg{};
   // optional per-kernel timing (lam_profile)
@@ -63,6 +68,9 @@ struct lam_plan_s {
   ~lam_plan_s() {
     for (auto& r : recs) { ev_pool.push_back(r.a); ev_pool.push_back(r.b); }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ev_ready[0], ev_ready[1], ev_freed[0], ev_freed[1], ev_start, ev_done})
+      if (e) (void)hipEventDestroy(e);
+    if (copy) (void)hipStreamDestroy(copy);
   }
 };
 
@@ -206,6 +214,16 @@ int build(lam_plan_s* P) {
   P->off_p = take((size_t)p.ntheta * p.h * p.w * P->csize);
   P->off_t = take((size_t)S * P->M1 * p.n2 * P->csize);
   P->off_g = take((size_t)S * P->M1 * P->M2 * P->csize);
+  // host streaming: y-slabs of the volume (real or complex) through two staging buffers of
+  // about 64 MiB; theta-slabs of the data go straight to / from the resident data buffer
+  {
+    const size_t row = (size_t)p.n0 * p.n2 * P->csize;          // one volume row (all z, all x)
+    P->ys = (int)std::max<size_t>(1, std::min<size_t>(p.n1, ((size_t)64 << 20) / row));
+    const size_t proj = (size_t)p.h * p.w * P->csize;
+    P->ts = (int)std::max<size_t>(1, std::min<size_t>(p.ntheta, ((size_t)64 << 20) / proj));
+    P->stage_bytes = align_up((size_t)P->ys * row);
+    P->off_stage = take(2 * P->stage_bytes);
+  }
   P->ws_need = o;
   // kernel dimensions
   Dims& D = P->D;
@@ -374,7 +392,8 @@ int run_fwd(lam_plan_s* P, const void* u, bool real_in, const void* dhat, void* 
   cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
   cpx<T>* o = reinterpret_cast<cpx<T>*>(out);
   const cpx<T>* dh = reinterpret_cast<const cpx<T>*>(dhat);
-  int rc = timed(P, K_ZFWD, s, "F_u1D", [&] { return launch_zfwd<T>(c, u, real_in, U1, D, tb, s); });
+  int rc = timed(P, K_ZFWD, s, "F_u1D",
+                 [&] { return launch_zfwd<T>(c, u, real_in, U1, 0, P->p.n1, (size_t)P->p.n1 * P->p.n2, D, tb, s); });
   for (int k0 = 0; !rc && k0 < P->p.h; k0 += P->slab) {
     const int ns = std::min(P->slab, P->p.h - k0);
     rc = timed(P, K_YCOL_FWD, s, "F_u2D y-FFT", [&] { return launch_ycol_fwd<T>(c, U1, Tb, k0, ns, D, tb, s); });
@@ -382,8 +401,10 @@ int run_fwd(lam_plan_s* P, const void* u, bool real_in, const void* dhat, void* 
     if (!rc) rc = timed(P, K_GATHER, s, "F_u2D gather", [&] { return launch_gather<T>(c, Gb, o, dh, k0, ns, D, tb, s); });
   }
   if (!rc && to_space) {
-    rc = timed(P, K_ROWFFT, s, "F*_2D rows", [&] { return launch_rowfft<T>(c, o, o, true, D, tb, s); });
-    if (!rc) rc = timed(P, K_COLFFT, s, "F*_2D columns", [&] { return launch_colfft<T>(c, o, o, true, inv_hw(P), D, tb, s); });
+    rc = timed(P, K_ROWFFT, s, "F*_2D rows", [&] { return launch_rowfft<T>(c, o, o, true, P->p.ntheta, D, tb, s); });
+    if (!rc)
+      rc = timed(P, K_COLFFT, s, "F*_2D columns",
+                 [&] { return launch_colfft<T>(c, o, o, true, inv_hw(P), P->p.ntheta, D, tb, s); });
   }
   return rc;
 }
@@ -400,8 +421,10 @@ int run_adj(lam_plan_s* P, const void* in, bool from_space, void* u, bool real_o
   const cpx<T>* r = reinterpret_cast<const cpx<T>*>(in);
   int rc = 0;
   if (from_space) {
-    rc = timed(P, K_ROWFFT, s, "F_2D rows", [&] { return launch_rowfft<T>(c, r, Pb, false, D, tb, s); });
-    if (!rc) rc = timed(P, K_COLFFT, s, "F_2D columns", [&] { return launch_colfft<T>(c, Pb, Pb, false, inv_hw(P), D, tb, s); });
+    rc = timed(P, K_ROWFFT, s, "F_2D rows", [&] { return launch_rowfft<T>(c, r, Pb, false, P->p.ntheta, D, tb, s); });
+    if (!rc)
+      rc = timed(P, K_COLFFT, s, "F_2D columns",
+                 [&] { return launch_colfft<T>(c, Pb, Pb, false, inv_hw(P), P->p.ntheta, D, tb, s); });
     r = Pb;
   }
   for (int k0 = 0; !rc && k0 < P->p.h; k0 += P->slab) {
@@ -410,7 +433,9 @@ int run_adj(lam_plan_s* P, const void* in, bool from_space, void* u, bool real_o
     if (!rc) rc = timed(P, K_XROW_ADJ, s, "F*_u2D x-FFT", [&] { return launch_xrow_adj<T>(c, Gb, Tb, ns, D, tb, s); });
     if (!rc) rc = timed(P, K_YCOL_ADJ, s, "F*_u2D y-FFT", [&] { return launch_ycol_adj<T>(c, Tb, U1, k0, ns, D, tb, s); });
   }
-  if (!rc) rc = timed(P, K_ZADJ, s, "F*_u1D", [&] { return launch_zadj<T>(c, U1, u, real_out, D, tb, s); });
+  if (!rc)
+    rc = timed(P, K_ZADJ, s, "F*_u1D",
+               [&] { return launch_zadj<T>(c, U1, u, real_out, 0, P->p.n1, (size_t)P->p.n1 * P->p.n2, D, tb, s); });
   return rc;
 }
 
@@ -420,9 +445,148 @@ int run_data_hat(lam_plan_s* P, const void* d, void* dhat, hipStream_t s) {
   const Tables<T> tb = tables<T>(P);
   const cpx<T>* in = reinterpret_cast<const cpx<T>*>(d);
   cpx<T>* o = reinterpret_cast<cpx<T>*>(dhat);
-  int rc = timed(P, K_ROWFFT, s, "W rows", [&] { return launch_rowfft<T>(P->cfg, in, o, false, P->D, tb, s); });
-  if (!rc) rc = timed(P, K_COLFFT, s, "W columns", [&] { return launch_colfft<T>(P->cfg, o, o, false, 1.0, P->D, tb, s); });
+  const int nt = P->p.ntheta;
+  int rc = timed(P, K_ROWFFT, s, "W rows", [&] { return launch_rowfft<T>(P->cfg, in, o, false, nt, P->D, tb, s); });
+  if (!rc)
+    rc = timed(P, K_COLFFT, s, "W columns", [&] { return launch_colfft<T>(P->cfg, o, o, false, 1.0, nt, P->D, tb, s); });
   return rc;
+}
+
+int stream_setup(lam_plan_s* P) {
+  if (P->copy) return LAM_OK;
+  hipError_t e = hipStreamCreateWithFlags(&P->copy, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&P->ev_ready[0], &P->ev_ready[1], &P->ev_freed[0], &P->ev_freed[1], &P->ev_start, &P->ev_done})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  return hip_status(e, "stream setup");
+}
+
+#define LAM_TRY(expr, what)                           \
+  do {                                                \
+    const int rc_ = hip_status((expr), what);         \
+    if (rc_) return rc_;                              \
+  } while (0)
+
+// d_host = L u_host with u and d in pinned host memory: y-slabs of u are
+// copied in on the plan's copy stream and consumed by the z step as they
+// land (two staging buffers); the 2D step runs on the resident stage
+// buffers; each theta-slab of d is copied out as soon as its 2D DFT is done.
+template <typename T>
+int run_fwd_streamed(lam_plan_s* P, const void* u_host, bool real_in, void* d_host, hipStream_t s) {
+  int rc = stream_setup(P);
+  if (rc) return rc;
+  const Tables<T> tb = tables<T>(P);
+  const LaunchCfg& c = P->cfg;
+  const Dims& D = P->D;
+  const lam_params& p = P->p;
+  const size_t es = real_in ? P->rsize : P->csize;
+  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(P->ws + P->off_u1);
+  cpx<T>* Pb = reinterpret_cast<cpx<T>*>(P->ws + P->off_p);
+  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(P->ws + P->off_t);
+  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
+  unsigned char* stage[2] = {P->ws + P->off_stage, P->ws + P->off_stage + P->stage_bytes};
+  LAM_TRY(hipEventRecord(P->ev_start, s), "stream start");
+  LAM_TRY(hipStreamWaitEvent(P->copy, P->ev_start, 0), "stream start");
+  for (int j = 0, y0 = 0; y0 < p.n1; y0 += P->ys, ++j) {
+    const int ny = std::min(P->ys, p.n1 - y0), b = j & 1;
+    if (j >= 2) LAM_TRY(hipStreamWaitEvent(P->copy, P->ev_freed[b], 0), "stage reuse");
+    LAM_TRY(hipMemcpy2DAsync(stage[b], (size_t)ny * p.n2 * es,
+                             static_cast<const unsigned char*>(u_host) + (size_t)y0 * p.n2 * es,
+                             (size_t)p.n1 * p.n2 * es, (size_t)ny * p.n2 * es, p.n0, hipMemcpyHostToDevice, P->copy),
+            "volume slab copy");
+    LAM_TRY(hipEventRecord(P->ev_ready[b], P->copy), "slab ready");
+    LAM_TRY(hipStreamWaitEvent(s, P->ev_ready[b], 0), "slab ready");
+    rc = timed(P, K_ZFWD, s, "F_u1D slab", [&] {
+      return launch_zfwd<T>(c, stage[b], real_in, U1, y0, ny, (size_t)ny * p.n2, D, tb, s);
+    });
+    if (rc) return rc;
+    LAM_TRY(hipEventRecord(P->ev_freed[b], s), "slab done");
+  }
+  for (int k0 = 0; !rc && k0 < p.h; k0 += P->slab) {
+    const int ns = std::min(P->slab, p.h - k0);
+    rc = timed(P, K_YCOL_FWD, s, "F_u2D y-FFT", [&] { return launch_ycol_fwd<T>(c, U1, Tb, k0, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_XROW_FWD, s, "F_u2D x-FFT", [&] { return launch_xrow_fwd<T>(c, Tb, Gb, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_GATHER, s, "F_u2D gather", [&] { return launch_gather<T>(c, Gb, Pb, nullptr, k0, ns, D, tb, s); });
+  }
+  const size_t proj = (size_t)p.h * p.w;
+  for (int j = 0, t0 = 0; !rc && t0 < p.ntheta; t0 += P->ts, ++j) {
+    const int nt = std::min(P->ts, p.ntheta - t0), b = j & 1;
+    cpx<T>* base = Pb + (size_t)t0 * proj;
+    rc = timed(P, K_ROWFFT, s, "F*_2D rows", [&] { return launch_rowfft<T>(c, base, base, true, nt, D, tb, s); });
+    if (!rc)
+      rc = timed(P, K_COLFFT, s, "F*_2D columns",
+                 [&] { return launch_colfft<T>(c, base, base, true, inv_hw(P), nt, D, tb, s); });
+    if (rc) return rc;
+    LAM_TRY(hipEventRecord(P->ev_ready[b], s), "projections ready");
+    LAM_TRY(hipStreamWaitEvent(P->copy, P->ev_ready[b], 0), "projections ready");
+    LAM_TRY(hipMemcpyAsync(static_cast<unsigned char*>(d_host) + (size_t)t0 * proj * P->csize, base,
+                           (size_t)nt * proj * P->csize, hipMemcpyDeviceToHost, P->copy),
+            "projection copy");
+  }
+  if (rc) return rc;
+  LAM_TRY(hipEventRecord(P->ev_done, P->copy), "stream done");
+  LAM_TRY(hipStreamWaitEvent(s, P->ev_done, 0), "stream done");
+  return LAM_OK;
+}
+
+// u_host = L* d_host (Re for a real volume), both in pinned host memory: theta-slabs
+// of d are copied into the resident data buffer and transformed as they land;
+// the z adjoint writes y-slabs into the staging buffers, copied out as they finish.
+template <typename T>
+int run_adj_streamed(lam_plan_s* P, const void* d_host, void* u_host, bool real_out, hipStream_t s) {
+  int rc = stream_setup(P);
+  if (rc) return rc;
+  const Tables<T> tb = tables<T>(P);
+  const LaunchCfg& c = P->cfg;
+  const Dims& D = P->D;
+  const lam_params& p = P->p;
+  const size_t es = real_out ? P->rsize : P->csize;
+  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(P->ws + P->off_u1);
+  cpx<T>* Pb = reinterpret_cast<cpx<T>*>(P->ws + P->off_p);
+  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(P->ws + P->off_t);
+  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
+  unsigned char* stage[2] = {P->ws + P->off_stage, P->ws + P->off_stage + P->stage_bytes};
+  LAM_TRY(hipEventRecord(P->ev_start, s), "stream start");
+  LAM_TRY(hipStreamWaitEvent(P->copy, P->ev_start, 0), "stream start");
+  const size_t proj = (size_t)p.h * p.w;
+  for (int j = 0, t0 = 0; t0 < p.ntheta; t0 += P->ts, ++j) {
+    const int nt = std::min(P->ts, p.ntheta - t0), b = j & 1;
+    cpx<T>* base = Pb + (size_t)t0 * proj;
+    LAM_TRY(hipMemcpyAsync(base, static_cast<const unsigned char*>(d_host) + (size_t)t0 * proj * P->csize,
+                           (size_t)nt * proj * P->csize, hipMemcpyHostToDevice, P->copy),
+            "projection copy");
+    LAM_TRY(hipEventRecord(P->ev_ready[b], P->copy), "projections ready");
+    LAM_TRY(hipStreamWaitEvent(s, P->ev_ready[b], 0), "projections ready");
+    rc = timed(P, K_ROWFFT, s, "F_2D rows", [&] { return launch_rowfft<T>(c, base, base, false, nt, D, tb, s); });
+    if (!rc)
+      rc = timed(P, K_COLFFT, s, "F_2D columns",
+                 [&] { return launch_colfft<T>(c, base, base, false, inv_hw(P), nt, D, tb, s); });
+    if (rc) return rc;
+  }
+  for (int k0 = 0; !rc && k0 < p.h; k0 += P->slab) {
+    const int ns = std::min(P->slab, p.h - k0);
+    rc = timed(P, K_SCATTER, s, "F*_u2D scatter", [&] { return launch_scatter<T>(c, Pb, Gb, k0, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_XROW_ADJ, s, "F*_u2D x-FFT", [&] { return launch_xrow_adj<T>(c, Gb, Tb, ns, D, tb, s); });
+    if (!rc) rc = timed(P, K_YCOL_ADJ, s, "F*_u2D y-FFT", [&] { return launch_ycol_adj<T>(c, Tb, U1, k0, ns, D, tb, s); });
+  }
+  if (rc) return rc;
+  for (int j = 0, y0 = 0; y0 < p.n1; y0 += P->ys, ++j) {
+    const int ny = std::min(P->ys, p.n1 - y0), b = j & 1;
+    if (j >= 2) LAM_TRY(hipStreamWaitEvent(s, P->ev_freed[b], 0), "stage reuse");
+    rc = timed(P, K_ZADJ, s, "F*_u1D slab", [&] {
+      return launch_zadj<T>(c, U1, stage[b], real_out, y0, ny, (size_t)ny * p.n2, D, tb, s);
+    });
+    if (rc) return rc;
+    LAM_TRY(hipEventRecord(P->ev_ready[b], s), "slab ready");
+    LAM_TRY(hipStreamWaitEvent(P->copy, P->ev_ready[b], 0), "slab ready");
+    LAM_TRY(hipMemcpy2DAsync(static_cast<unsigned char*>(u_host) + (size_t)y0 * p.n2 * es, (size_t)p.n1 * p.n2 * es,
+                             stage[b], (size_t)ny * p.n2 * es, (size_t)ny * p.n2 * es, p.n0, hipMemcpyDeviceToHost,
+                             P->copy),
+            "volume slab copy");
+    LAM_TRY(hipEventRecord(P->ev_freed[b], P->copy), "slab copied");
+  }
+  LAM_TRY(hipEventRecord(P->ev_done, P->copy), "stream done");
+  LAM_TRY(hipStreamWaitEvent(s, P->ev_done, 0), "stream done");
+  return LAM_OK;
 }
 
 int fwd_any(lam_plan p, const void* u, bool real_in, const void* dhat, void* out, bool to_space, void* stream) {
@@ -546,6 +710,37 @@ int lam_fwd_hat(lam_plan p, const void* u, const void* dhat, void* r, void* s) {
   return fwd_any(p, u, false, dhat, r, false, s);
 }
 int lam_adj_hat(lam_plan p, const void* r, void* u, void* s) { g_last_error.clear(); return adj_any(p, r, false, u, false, s); }
+
+int lam_fwd_streamed(lam_plan p, const void* u_host, int u_real, void* d_host, void* stream) {
+  g_last_error.clear();
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!u_host || !d_host) return fail(LAM_ERR_ARG, "null array pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return p->p.dtype == LAM_C64 ? run_fwd_streamed<float>(p, u_host, u_real != 0, d_host, s)
+                               : run_fwd_streamed<double>(p, u_host, u_real != 0, d_host, s);
+}
+
+int lam_adj_streamed(lam_plan p, const void* d_host, void* u_host, int u_real, void* stream) {
+  g_last_error.clear();
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!u_host || !d_host) return fail(LAM_ERR_ARG, "null array pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return p->p.dtype == LAM_C64 ? run_adj_streamed<float>(p, d_host, u_host, u_real != 0, s)
+                               : run_adj_streamed<double>(p, d_host, u_host, u_real != 0, s);
+}
+
+int lam_stream_slabs(lam_plan p, int y_rows, int theta_proj) {
+  if (!p) return fail(LAM_ERR_ARG, "null plan");
+  const size_t row = (size_t)p->p.n0 * p->p.n2 * p->csize;
+  if (y_rows < 1 || y_rows > p->p.n1 || (size_t)y_rows * row > p->stage_bytes)
+    return fail(LAM_ERR_ARG, "y_rows must be in [1, n1] and fit the staging buffers");
+  if (theta_proj < 1 || theta_proj > p->p.ntheta) return fail(LAM_ERR_ARG, "theta_proj must be in [1, ntheta]");
+  p->ys = y_rows;
+  p->ts = theta_proj;
+  return LAM_OK;
+}
 
 int lam_data_hat(lam_plan p, const void* d, void* dhat, void* stream) {
   g_last_error.clear();

@@ -47,11 +47,13 @@ struct LaunchCfg {
 };
 
 template <typename T>
-hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, const Dims& D, const Tables<T>& tb,
-                       hipStream_t s);
+// z step over the volume rows [y0, y0 + ny); the slab buffer holds those rows with z stride zs elements
+// (zs = n1 n2 for the whole volume)
+hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, int y0, int ny, size_t in_zs,
+                       const Dims& D, const Tables<T>& tb, hipStream_t s);
 template <typename T>
-hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, const Dims& D,
-                       const Tables<T>& tb, hipStream_t s);
+hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, int y0, int ny, size_t out_zs,
+                       const Dims& D, const Tables<T>& tb, hipStream_t s);
 template <typename T>
 hipError_t launch_ycol_fwd(const LaunchCfg& c, const cpx<T>* u1, cpx<T>* Tb, int k0, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s);
@@ -77,10 +79,10 @@ template <typename T>
 hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, const int* offs,
                             int* lists, hipStream_t s);
 template <typename T>
-hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
+hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, int nproj, const Dims& D,
                          const Tables<T>& tb, hipStream_t s);
 template <typename T>
-hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale,
+hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale, int nproj,
                          const Dims& D, const Tables<T>& tb, hipStream_t s);
 
 }  // namespace lam

@@ -28,10 +28,11 @@ __device__ __forceinline__ int sgn_parity(int k) { return (k & 1) ? -1 : 1; }
 // ---------------------------------------------------------------------------
 template <typename T, int MH, bool REAL_IN>
 __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx<T>* __restrict__ u1, Dims D,
-                                               Tables<T> tb, int log2TX) {
+                                               Tables<T> tb, int log2TX, int y0, size_t in_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int TX = 1 << log2TX, M0 = 1 << D.log2M0, n0 = D.n0;
-  const int x0 = blockIdx.x * TX, y = blockIdx.y;
+  // blockIdx.y is the row within the input slab; y the row of the volume
+  const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   const int tid = threadIdx.x, nth = blockDim.x;
   const size_t plane = (size_t)D.n1 * D.n2;
   const cpx<T> zero = mk((T)0, (T)0);
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
     for (int it = 0; it < vpt<T>(); ++it) {
       const int e = min(tid + it * nth, n0 * TX - 1);    // clamped: every load is issued unconditionally
       const int a = e >> log2TX, b = e & (TX - 1);
-      const size_t gi = (size_t)a * plane + (size_t)y * D.n2 + x0 + b;
+      const size_t gi = (size_t)a * in_zs + (size_t)yl * D.n2 + x0 + b;
       if constexpr (REAL_IN) v[it] = mk(reinterpret_cast<const T*>(uin)[gi], (T)0);
       else v[it] = reinterpret_cast<const cpx<T>*>(uin)[gi];
     }
@@ -81,10 +82,11 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
 // deconvolve.
 template <typename T, int MH, bool REAL_OUT>
 __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, void* __restrict__ uout, Dims D,
-                                               Tables<T> tb, int log2TX) {
+                                               Tables<T> tb, int log2TX, int y0, size_t out_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int TX = 1 << log2TX, M0 = 1 << D.log2M0, n0 = D.n0;
-  const int x0 = blockIdx.x * TX, y = blockIdx.y;
+  // blockIdx.y is the row within the output slab; y the row of the volume
+  const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   const int tid = threadIdx.x, nth = blockDim.x;
   const size_t plane = (size_t)D.n1 * D.n2;
   for (int e0 = 0; e0 < D.h * TX; e0 += vpt<T>() * nth) {
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     const int a = e >> log2TX, b = e & (TX - 1);
     const cpx<T> g = buf[((a - n0 / 2) & (M0 - 1)) * TX + b];
     const T c = tb.cz[a];
-    const size_t gi = (size_t)a * plane + (size_t)y * D.n2 + x0 + b;
+    const size_t gi = (size_t)a * out_zs + (size_t)yl * D.n2 + x0 + b;
     if constexpr (REAL_OUT) reinterpret_cast<T*>(uout)[gi] = g.x * c;
     else reinterpret_cast<cpx<T>*>(uout)[gi] = mk(g.x * c, -g.y * c);
   }
@@ -358,38 +360,38 @@ static hipError_t prep(Kern k, size_t lds) {
   }
 
 template <typename T>
-hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, const Dims& D, const Tables<T>& tb,
-                       hipStream_t s) {
-  dim3 grid(D.n2 >> c.z_log2TX, D.n1);
+hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, int y0, int ny, size_t in_zs,
+                       const Dims& D, const Tables<T>& tb, hipStream_t s) {
+  dim3 grid(D.n2 >> c.z_log2TX, ny);
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
     if (real_in) {
       auto k = k_zfwd<T, MH, true>;
       if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u, u1, D, tb, c.z_log2TX);
+      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
     } else {
       auto k = k_zfwd<T, MH, false>;
       if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u, u1, D, tb, c.z_log2TX);
+      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
     }
   });
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, const Dims& D,
-                       const Tables<T>& tb, hipStream_t s) {
-  dim3 grid(D.n2 >> c.z_log2TX, D.n1);
+hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, int y0, int ny, size_t out_zs,
+                       const Dims& D, const Tables<T>& tb, hipStream_t s) {
+  dim3 grid(D.n2 >> c.z_log2TX, ny);
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
     if (real_out) {
       auto k = k_zadj<T, MH, true>;
       if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u1, u, D, tb, c.z_log2TX);
+      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
     } else {
       auto k = k_zadj<T, MH, false>;
       if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u1, u, D, tb, c.z_log2TX);
+      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
     }
   });
   return hipGetLastError();
@@ -440,36 +442,36 @@ hipError_t launch_ycol_adj(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* u1, int
 }
 
 template <typename T>
-hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, const Dims& D,
+hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, int nproj, const Dims& D,
                          const Tables<T>& tb, hipStream_t s) {
   const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
   auto k = k_rowfft<T>;
   hipError_t e = prep(k, c.r_lds);
   if (e != hipSuccess) return e;
-  const size_t rows = (size_t)D.ntheta * D.h;
+  const size_t rows = (size_t)nproj * D.h;
   hipLaunchKernelGGL(k, dim3((unsigned)(rows >> c.r_log2RB)), dim3(c.r_threads), c.r_lds, s, in, out, log2w, log2h,
                      c.r_log2RB, inverse ? 1 : 0, tb);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale_d,
+hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale_d, int nproj,
                          const Dims& D, const Tables<T>& tb, hipStream_t s) {
   const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
   auto k = k_colfft<T>;
   hipError_t e = prep(k, c.c_lds);
   if (e != hipSuccess) return e;
   const T scale = (T)scale_d;
-  hipLaunchKernelGGL(k, dim3(D.w >> c.c_log2TX, D.ntheta), dim3(c.c_threads), c.c_lds, s, in, out, log2h, log2w,
+  hipLaunchKernelGGL(k, dim3(D.w >> c.c_log2TX, nproj), dim3(c.c_threads), c.c_lds, s, in, out, log2h, log2w,
                      c.c_log2TX, inverse ? 1 : 0, scale, tb);
   return hipGetLastError();
 }
 
 #define LAM_INST(T)                                                                                              \
-  template hipError_t launch_zfwd<T>(const LaunchCfg&, const void*, bool, cpx<T>*, const Dims&, const Tables<T>&, \
-                                     hipStream_t);                                                               \
-  template hipError_t launch_zadj<T>(const LaunchCfg&, const cpx<T>*, void*, bool, const Dims&, const Tables<T>&, \
-                                     hipStream_t);                                                               \
+  template hipError_t launch_zfwd<T>(const LaunchCfg&, const void*, bool, cpx<T>*, int, int, size_t, const Dims&,  \
+                                     const Tables<T>&, hipStream_t);                                             \
+  template hipError_t launch_zadj<T>(const LaunchCfg&, const cpx<T>*, void*, bool, int, int, size_t, const Dims&,  \
+                                     const Tables<T>&, hipStream_t);                                             \
   template hipError_t launch_ycol_fwd<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, int, int, const Dims&,        \
                                          const Tables<T>&, hipStream_t);                                         \
   template hipError_t launch_xrow_fwd<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, int, const Dims&,             \
@@ -478,9 +480,9 @@ hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool
                                          const Tables<T>&, hipStream_t);                                         \
   template hipError_t launch_ycol_adj<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, int, int, const Dims&,        \
                                          const Tables<T>&, hipStream_t);                                         \
-  template hipError_t launch_rowfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, const Dims&,              \
+  template hipError_t launch_rowfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, int, const Dims&,         \
                                        const Tables<T>&, hipStream_t);                                           \
-  template hipError_t launch_colfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, double, const Dims&,      \
+  template hipError_t launch_colfft<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, bool, double, int, const Dims&, \
                                        const Tables<T>&, hipStream_t);
 
 LAM_INST(float)

@@ -72,6 +72,9 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_fwd_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_data_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        L.lam_fwd_streamed.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p]
+        L.lam_adj_streamed.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+        L.lam_stream_slabs.argtypes = [c_void_p, c_int, c_int]
         L.lam_admm_work_bytes.argtypes = [c_void_p]
         L.lam_admm_work_bytes.restype = c_size_t
         L.lam_admm_step.argtypes = [c_void_p, POINTER(AdmmState), c_void_p, c_int, c_void_p]
@@ -197,6 +200,49 @@ class Plan:
         self._arr(d, self.data_shape, "d")
         out = torch.empty(self.data_shape, dtype=self.dtype, device=self.device) if out is None else out
         _check(lib().lam_data_hat(self._h, c_void_p(d.data_ptr()), c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    # ---------------------------------------------------------------- host-streamed
+    def _host(self, x: torch.Tensor, shape, what: str, allow_real=False) -> torch.Tensor:
+        if x.device.type != "cpu" or not x.is_pinned():
+            raise ValueError(f"{what}: expected a pinned host tensor (pin_memory=True)")
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(x.shape)}")
+        ok = (self.dtype,) + ((self.rdtype,) if allow_real else ())
+        if x.dtype not in ok:
+            raise ValueError(f"{what}: expected dtype in {ok}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{what}: tensor must be contiguous")
+        return x
+
+    def stream_slabs(self, y_rows: int, theta_proj: int):
+        """Slab sizes of the host-streamed calls: volume rows per y-slab, projections per theta-slab."""
+        _check(lib().lam_stream_slabs(self._h, int(y_rows), int(theta_proj)))
+
+    def fwd_streamed(self, u: torch.Tensor, out: torch.Tensor | None = None, wait: bool = True) -> torch.Tensor:
+        """d = L u with u and d in pinned host memory, slab copies overlapped with the kernels."""
+        self._host(u, self.vol_shape, "u", allow_real=True)
+        out = torch.empty(self.data_shape, dtype=self.dtype, pin_memory=True) if out is None else out
+        self._host(out, self.data_shape, "d")
+        _check(lib().lam_fwd_streamed(self._h, c_void_p(u.data_ptr()), 0 if u.is_complex() else 1,
+                                      c_void_p(out.data_ptr()), self._stream()))
+        if wait:
+            torch.cuda.current_stream(self.device).synchronize()
+        return out
+
+    def adj_streamed(self, d: torch.Tensor, real: bool = False, out: torch.Tensor | None = None,
+                     wait: bool = True) -> torch.Tensor:
+        """u = L* d (Re if real) with d and u in pinned host memory."""
+        self._host(d, self.data_shape, "d")
+        dt = self.rdtype if real else self.dtype
+        out = torch.empty(self.vol_shape, dtype=dt, pin_memory=True) if out is None else out
+        self._host(out, self.vol_shape, "u", allow_real=True)
+        if out.dtype != dt:
+            raise ValueError(f"u: expected dtype {dt}")
+        _check(lib().lam_adj_streamed(self._h, c_void_p(d.data_ptr()), c_void_p(out.data_ptr()),
+                                      1 if real else 0, self._stream()))
+        if wait:
+            torch.cuda.current_stream(self.device).synchronize()
         return out
 
     # ---------------------------------------------------------------- timing

@@ -68,8 +68,9 @@ def test_workspace_size_and_state_errors():
     assert lib.lam_init(byref(h), byref(_params(dtype=0, slab=4))) == 0
     nb = lib.lam_workspace_bytes(h)
     # u1 (h n1 n2) + P (ntheta h w) + T (slab M1 n2) + G (slab M1 M2), complex64, the per-tile
-    # target lists (one int per target) plus small tables
-    big = (32 * 32 * 32 + 32 * 32 * 32 + 4 * 64 * 32 + 4 * 64 * 64) * 8 + 32 * 32 * 32 * 4
+    # target lists (one int per target), two host-streaming staging buffers (here the whole
+    # volume each) plus small tables
+    big = (32 * 32 * 32 + 32 * 32 * 32 + 4 * 64 * 32 + 4 * 64 * 64 + 2 * 32 * 32 * 32) * 8 + 32 * 32 * 32 * 4
     assert big <= nb <= big + 64 * 1024
     h2 = c_void_p()
     assert lib.lam_init(byref(h2), byref(_params(dtype=1, slab=4))) == 0
@@ -81,6 +82,13 @@ def test_workspace_size_and_state_errors():
     assert lib.lam_set_workspace(h, c_void_p(0x1001), nb) == 1
     assert lib.lam_set_workspace(h, c_void_p(0x1000), nb - 1) == 4
     assert lib.lam_set_workspace(h, c_void_p(None), nb) == 1
+    # host-streaming slab sizes
+    assert lib.lam_stream_slabs(h, 0, 4) == 1
+    assert lib.lam_stream_slabs(h, 33, 4) == 1
+    assert lib.lam_stream_slabs(h, 8, 33) == 1
+    assert lib.lam_stream_slabs(h, 8, 5) == 0
+    assert lib.lam_stream_slabs(None, 8, 5) == 1
+    assert lib.lam_fwd_streamed(h, c_void_p(256), 1, c_void_p(512), None) == 4
     lib.lam_destroy(h)
     lib.lam_destroy(h2)
     lib.lam_destroy(None)
