@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle accuracy check")
+    ap.add_argument("--slab", type=int, default=0, help="k_v slices per 2D-step slab (0: automatic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
@@ -161,7 +162,7 @@ def main():
     dev = torch.device("cuda:0")
     log(f"[bench] workload {args.workload}: n={n} ntheta={nt} det={h} phi={wl['phi_deg']} c64")
 
-    plan = lam.Plan(n, ntheta=nt, phi=phi, h=h, w=h, dtype=torch.complex64, device=dev)
+    plan = lam.Plan(n, ntheta=nt, phi=phi, h=h, w=h, dtype=torch.complex64, device=dev, slab=args.slab)
     blobs = I.draw_blobs(wl["seed"], wl["nblobs"], cube_layer=wl["cubes"], n=n)
     u = I.blob_phantom_torch((n, n, n), blobs, dev, torch.float32).to(torch.complex64)
     d = I.random_complex_torch((nt, h, h), wl["seed"] + 200, dev, torch.complex64)

@@ -62,6 +62,13 @@ __device__ __forceinline__ int axis_intervals(double A, double iA, double B, int
     if (n < 2) { lo[n] = a; hi[n] = b; ++n; }
     else { lo[1] = min(lo[1], a); hi[1] = max(hi[1], b); }
   }
+  // the generous bounds let the intervals of neighbouring images overlap when
+  // the band spans most of the period; visit their union so no k_u comes twice
+  if (n == 2 && lo[1] <= hi[0] + 1 && lo[0] <= hi[1] + 1) {
+    lo[0] = min(lo[0], lo[1]);
+    hi[0] = max(hi[0], hi[1]);
+    n = 1;
+  }
   return n;
 }
 

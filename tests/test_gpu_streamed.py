@@ -27,7 +27,7 @@ def rel(a, b):
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
 @pytest.mark.parametrize("slabs", [(20, 13), (1, 1), None], ids=["ragged", "single", "auto"])
 def test_streamed_matches_resident(L, dtype, slabs):
-    n, nt = 96, 40
+    n, nt = 64, 40
     plan = L.Plan(n, ntheta=nt, phi=math.radians(25), dtype=dtype)
     if slabs is not None:
         plan.stream_slabs(*slabs)
