@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "lam.h"
@@ -49,7 +50,7 @@ struct lam_plan_s {
   std::vector<double> zq_w;
   // workspace layout (byte offsets)
   size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zw = 0, off_cth = 0, off_sth = 0,
-         off_rc = 0, off_line = 0, off_zq_ptr = 0, off_zq_av = 0, off_zq_w = 0, off_tlist = 0, off_toff = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
+         off_rc = 0, off_line = 0, off_zq_ptr = 0, off_zq_av = 0, off_zq_w = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   int ntx = 1, nty = 1;        // tiles of the oversampled grid per slice
@@ -210,6 +211,8 @@ int build(lam_plan_s* P) {
   P->nty = P->M1 / TS;
   P->off_tlist = take((size_t)p.h * p.ntheta * p.w * sizeof(int));
   P->off_toff = take((size_t)p.h * ((size_t)P->ntx * P->nty * 9 + 1) * sizeof(int));
+  P->off_gperm = take((size_t)p.h * P->ntx * P->nty * sizeof(int));
+  P->off_sperm = take((size_t)p.h * P->ntx * P->nty * sizeof(int));
   P->off_u1 = take((size_t)p.h * p.n1 * p.n2 * P->csize);
   P->off_p = take((size_t)p.ntheta * p.h * p.w * P->csize);
   P->off_t = take((size_t)S * P->M1 * p.n2 * P->csize);
@@ -283,6 +286,8 @@ Tables<T> tables(const lam_plan_s* P) {
   t.line = reinterpret_cast<const double*>(w + P->off_line);
   t.tlist = reinterpret_cast<const int*>(w + P->off_tlist);
   t.toff = reinterpret_cast<const int*>(w + P->off_toff);
+  t.gperm = reinterpret_cast<const int*>(w + P->off_gperm);
+  t.sperm = reinterpret_cast<const int*>(w + P->off_sperm);
   t.zq_ptr = reinterpret_cast<const int*>(w + P->off_zq_ptr);
   t.zq_av = reinterpret_cast<const int*>(w + P->off_zq_av);
   t.zq_w = reinterpret_cast<const T*>(w + P->off_zq_w);
@@ -373,6 +378,32 @@ int build_lists(lam_plan_s* P) {
   }
   e = hipMemcpy(toff, cnt.data(), cnt.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_status(e, "target offset copy");
+  // per slice, the tiles in decreasing order of work (targets gathered, targets spread): the
+  // kernels start the heaviest tiles first so that the dense tiles near the frequency origin do
+  // not form the tail of a launch
+  const int ntiles = P->ntx * P->nty;
+  std::vector<int> gperm((size_t)h * ntiles), sperm((size_t)h * ntiles), work(ntiles);
+  for (int k = 0; k < h; ++k) {
+    const int* of = &cnt[(size_t)k * per_slice];
+    int* gp = &gperm[(size_t)k * ntiles];
+    int* sp = &sperm[(size_t)k * ntiles];
+    for (int i = 0; i < ntiles; ++i) {
+      gp[i] = sp[i] = i;
+      work[i] = of[i * 9 + 9] - of[i * 9];
+    }
+    std::stable_sort(gp, gp + ntiles, [&](int a, int b) { return work[a] > work[b]; });
+    for (int i = 0; i < ntiles; ++i) {
+      int b[13], en[13];
+      const int nr = spread_ranges(of, P->ntx, P->nty, i / P->ntx, i % P->ntx, b, en);
+      work[i] = 0;
+      for (int j = 0; j < nr; ++j) work[i] += en[j] - b[j];
+    }
+    std::stable_sort(sp, sp + ntiles, [&](int a, int b) { return work[a] > work[b]; });
+  }
+  e = hipMemcpy(P->ws + P->off_gperm, gperm.data(), gperm.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(P->ws + P->off_sperm, sperm.data(), sperm.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_status(e, "tile order copy");
   for (int k0 = 0; k0 < h; k0 += chunk) {
     const int rc = hip_status(launch_list_fill<T>(P->cfg, k0, std::min(chunk, h - k0), P->D, tb, toff, tlist, nullptr),
                               "target fill");

@@ -150,8 +150,10 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
   const int ntx = M2 >> log2TS, nty = M1 >> log2TS;
   const int tid = threadIdx.x, nth = blockDim.x;
   cpx<T>* tile = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int kk = blockIdx.z, k = k0 + kk;
-  const int tx = blockIdx.x, ty = blockIdx.y;
+  // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
+  const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
+  const int tix = tb.gperm[(size_t)k * ntx * nty + rank];
+  const int tx = tix % ntx, ty = tix / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
   const cpx<T>* G = Gb + (size_t)kk * M1 * M2;
   // e / P by multiplication: exact for e < 2^16 with P < 2^8
@@ -227,34 +229,19 @@ __global__ __launch_bounds__(1024) void k_scatter(const cpx<T>* __restrict__ in,
   T* rec = reinterpret_cast<T*>(aim + TS * PA);                 // [nth][RS]
   int* corner = reinterpret_cast<int*>(rec + (size_t)nth * RS); // [nth]
   int* rng = corner + nth;                                      // [2][14]: starts, prefix counts
-  const int kk = blockIdx.z, k = k0 + kk;
-  const int tx = blockIdx.x, ty = blockIdx.y;
+  // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
+  const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
+  const int tile = tb.sperm[(size_t)k * ntx * nty + rank];
+  const int tx = tile % ntx, ty = tile / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
   for (int e = tid; e < 2 * TS * PA; e += nth) are[e] = 0.0;
   const size_t per_slice = (size_t)ntx * nty * 9 + 1;
   const int* of = tb.toff + (size_t)k * per_slice;
   if (tid == 0) {
-    // own tile (all classes), then the border classes of the neighbours whose stencils reach in
-    int nr = 0, tot = 0;
-    auto add = [&](int tyy, int txx, int c0, int c1) {
-      const int* o = of + (size_t)(tyy * ntx + txx) * 9;
-      const int b = o[c0], e = o[c1];
-      if (e > b) { rng[nr] = b; rng[14 + nr] = tot; tot += e - b; ++nr; }
-    };
-    add(ty, tx, 0, 9);
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        if ((dx == 0 && dy == 0) || (dx != 0 && ntx == 1) || (dy != 0 && nty == 1)) continue;
-        const int nty_ = (ty + dy + nty) % nty, ntx_ = (tx + dx + ntx) % ntx;
-        const int cx = dx < 0 ? 2 : 0, cy = dy < 0 ? 2 : 0;     // the neighbour's border facing this tile
-        if (dy == 0) {
-          for (int c = 0; c < 3; ++c) add(nty_, ntx_, 3 * c + cx, 3 * c + cx + 1);
-        } else if (dx == 0) {
-          add(nty_, ntx_, 3 * cy, 3 * cy + 3);
-        } else {
-          add(nty_, ntx_, 3 * cy + cx, 3 * cy + cx + 1);
-        }
-      }
+    int b[13], e[13];
+    const int nr = spread_ranges(of, ntx, nty, ty, tx, b, e);
+    int tot = 0;
+    for (int j = 0; j < nr; ++j) { rng[j] = b[j]; rng[14 + j] = tot; tot += e[j] - b[j]; }
     rng[14 + nr] = tot;
     rng[13] = nr;
   }
@@ -364,8 +351,8 @@ hipError_t launch_gather(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* out, cons
   LAM_MH_SWITCH(D.m, {
     auto k = k_gather<T, MH>;
     if ((e = prep(k, c.g_lds)) != hipSuccess) return e;
-    dim3 grid((1 << D.log2M2) >> c.g_log2TS, (1 << D.log2M1) >> c.g_log2TS, ns);
-    hipLaunchKernelGGL(k, grid, dim3(c.g_threads), c.g_lds, s, Gb, out, dhat, k0, D, tb, c.g_log2TS);
+    const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
+    hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.g_threads), c.g_lds, s, Gb, out, dhat, k0, D, tb, c.g_log2TS);
   });
   return hipGetLastError();
 }
@@ -377,8 +364,8 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
   LAM_MH_SWITCH(D.m, {
     auto k = k_scatter<T, MH>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
-    dim3 grid((1 << D.log2M2) >> c.g_log2TS, (1 << D.log2M1) >> c.g_log2TS, ns);
-    hipLaunchKernelGGL(k, grid, dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
+    const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
+    hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
   });
   return hipGetLastError();
 }

@@ -33,7 +33,38 @@ struct Tables {
   const T* zq_w;      // [h 2m] weight of each entry
   const int* tlist;   // per slice [n_theta w]: targets sorted by (tile, border class), t * 4096 + k_u index
   const int* toff;    // per slice [n_tiles 9 + 1]: offsets of the (tile, class) lists within the slice
+  const int* gperm;   // per slice [n_tiles]: tiles in decreasing order of gather work
+  const int* sperm;   // per slice [n_tiles]: tiles in decreasing order of spread work
 };
+
+// The list ranges [b, e) of one slice that tile (ty, tx) consumes in the adjoint
+// spread: its own list (all border classes), then the border classes of the
+// neighbouring tiles whose stencils reach into it (the facing column of a left /
+// right neighbour, the facing row of an upper / lower one, the facing corner of
+// a diagonal one).  of: the slice's [n_tiles 9 + 1] offsets.  Returns the number
+// of non-empty ranges (at most 13).
+__host__ __device__ inline int spread_ranges(const int* of, int ntx, int nty, int ty, int tx, int* b, int* e) {
+  int nr = 0;
+  auto add = [&](int tyy, int txx, int c0, int c1) {
+    const int* o = of + (tyy * ntx + txx) * 9;
+    if (o[c1] > o[c0]) { b[nr] = o[c0]; e[nr] = o[c1]; ++nr; }
+  };
+  add(ty, tx, 0, 9);
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      if ((dx == 0 && dy == 0) || (dx != 0 && ntx == 1) || (dy != 0 && nty == 1)) continue;
+      const int ny_ = (ty + dy + nty) % nty, nx_ = (tx + dx + ntx) % ntx;
+      const int cx = dx < 0 ? 2 : 0, cy = dy < 0 ? 2 : 0;     // the neighbour's border facing this tile
+      if (dy == 0) {
+        for (int c = 0; c < 3; ++c) add(ny_, nx_, 3 * c + cx, 3 * c + cx + 1);
+      } else if (dx == 0) {
+        add(ny_, nx_, 3 * cy, 3 * cy + 3);
+      } else {
+        add(ny_, nx_, 3 * cy + cx, 3 * cy + cx + 1);
+      }
+    }
+  return nr;
+}
 
 // Launch shapes chosen by the host plan.
 struct LaunchCfg {
