@@ -108,7 +108,7 @@ void row_cfg(int log2N, long nrows, size_t csize, int& log2RB, int& threads, siz
   while (RB > 1 && (RB > nrows || N * RB * (long)csize > 32768 || N * RB / vp > 1024 || nrows % RB)) RB >>= 1;
   log2RB = ilog2(RB);
   threads = (int)std::max<long>(64, N * RB / vp);
-  lds = (size_t)N * RB * csize;
+  lds = (size_t)N * RB * csize * 9 / 8;     // one pad slot per 8 elements (bank spreading)
 }
 
 int build(lam_plan_s* P) {

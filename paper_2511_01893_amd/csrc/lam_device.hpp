@@ -79,7 +79,13 @@ template <typename T, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
 // to (j, b) map: batch index fastest (for interleaved [p][b] layouts) or
 // butterfly index fastest (for contiguous rows).
 // ---------------------------------------------------------------------------
-template <typename T, int R, int VPT>
+// LDS element index of the FFT buffers, optionally with one pad slot per 8
+// elements.  Without it, a row-major buffer's first Stockham stages store at
+// strides of 8 and 64 elements, which puts a wave's 64 lanes on a handful of
+// banks; with it, those stores spread over every bank.
+template <bool PAD> __device__ __forceinline__ int lpad(int e) { return PAD ? e + (e >> 3) : e; }
+
+template <typename T, int R, int VPT, bool PAD = false>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, int Ns, int log2span, int sp, int sb,
                                           bool bfast, const cpx<T>* __restrict__ tw, int log2tw) {
   constexpr int IT = VPT / R;
@@ -97,7 +103,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, in
       if (bfast) { b = t & ((1 << log2nb) - 1); j = t >> log2nb; }
       else { j = t & (nbf - 1); b = t >> log2nbf; }
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * nbf) * sp + b * sb];
+      for (int r = 0; r < R; ++r) v[it][r] = buf[lpad<PAD>((j + r * nbf) * sp + b * sb)];
     }
   }
   __syncthreads();
@@ -115,25 +121,25 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, in
       dftR<T, R>(v[it]);
       const int idxD = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(idxD + r * Ns) * sp + b * sb] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[lpad<PAD>((idxD + r * Ns) * sp + b * sb)] = v[it][r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int VPT>
+template <typename T, int VPT, bool PAD = false>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int log2n, int log2nb, int sp, int sb, bool bfast,
                         const cpx<T>* __restrict__ tw, int log2tw) {
   int Ns = 1, lspan = 0, rem = log2n;
   while (rem > 0) {
     if (rem >= 3) {
-      fft_stage<T, 8, VPT>(buf, log2n, log2nb, Ns, lspan + 3, sp, sb, bfast, tw, log2tw);
+      fft_stage<T, 8, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 3, sp, sb, bfast, tw, log2tw);
       Ns <<= 3; lspan += 3; rem -= 3;
     } else if (rem == 2) {
-      fft_stage<T, 4, VPT>(buf, log2n, log2nb, Ns, lspan + 2, sp, sb, bfast, tw, log2tw);
+      fft_stage<T, 4, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 2, sp, sb, bfast, tw, log2tw);
       Ns <<= 2; lspan += 2; rem -= 2;
     } else {
-      fft_stage<T, 2, VPT>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw);
+      fft_stage<T, 2, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw);
       Ns <<= 1; lspan += 1; rem -= 1;
     }
   }

@@ -227,14 +227,14 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
       const int e = tid + it * nth;
       if (e < RB * n2) {
         const int b = e >> log2n2, a = e & (n2 - 1);
-        buf[b * M2 + n2 / 2 + a] = zero;
-        buf[b * M2 + ((a - n2 / 2) & (M2 - 1))] = v[it];
+        buf[lpad<true>(b * M2 + n2 / 2 + a)] = zero;
+        buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))] = v[it];
       }
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw);
-  for (int e = tid; e < RB * M2; e += nth) Gb[r0 * M2 + e] = buf[e];
+  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw);
+  for (int e = tid; e < RB * M2; e += nth) Gb[r0 * M2 + e] = buf[lpad<true>(e)];
 }
 
 template <typename T>
@@ -254,14 +254,14 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
       const int e = tid + it * nth;
-      if (e < RB * M2) buf[e] = conj(v[it]);
+      if (e < RB * M2) buf[lpad<true>(e)] = conj(v[it]);
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw);
   for (int e = tid; e < RB * n2; e += nth) {
     const int b = e >> log2n2, a = e & (n2 - 1);
-    Tb[(r0 + b) * n2 + a] = conj(buf[b * M2 + ((a - n2 / 2) & (M2 - 1))]);
+    Tb[(r0 + b) * n2 + a] = conj(buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))]);
   }
 }
 
@@ -293,14 +293,14 @@ __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, 
         const int b = e >> log2L, p = e & (L - 1);
         const int arow = (int)((r0 + b) & hmask);
         cpx<T> v = inverse ? conj(w[it]) : w[it];
-        buf[e] = sgn_parity(arow + p) > 0 ? v : mk(-v.x, -v.y);
+        buf[lpad<true>(e)] = sgn_parity(arow + p) > 0 ? v : mk(-v.x, -v.y);
       }
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, log2L, log2RB, 1, L, false, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>(), true>(buf, log2L, log2RB, 1, L, false, tb.tw, tb.log2tw);
   for (int e = tid; e < RB * L; e += nth) {
-    const cpx<T> v = buf[e];
+    const cpx<T> v = buf[lpad<true>(e)];
     out[r0 * L + e] = inverse ? conj(v) : v;
   }
 }
