@@ -135,6 +135,31 @@ def sampled_oracle_check(plan, u_host, kv_list):
     return O.relerr(got.astype(np.complex128), ref)
 
 
+def source_digest() -> str:
+    """SHA-256 over the HIP sources: counter-derived figures are valid only for the kernels they were taken on."""
+    import hashlib
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_01893_amd", "csrc")
+    hsh = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            hsh.update(f.encode())
+            hsh.update(open(os.path.join(csrc, f), "rb").read())
+    return hsh.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str, slab: int):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading),
+    from the committed counter summary of this workload; None if there is none, it was taken with
+    another slab, or the kernels have changed since."""
+    f = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(f):
+        return None
+    t = json.load(open(f))
+    if t.get("source_sha256") != source_digest() or t.get("slab") != slab or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["hbm_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +170,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle accuracy check")
     ap.add_argument("--slab", type=int, default=0, help="k_v slices per 2D-step slab (0: automatic)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
@@ -167,6 +194,14 @@ def main():
     u = I.blob_phantom_torch((n, n, n), blobs, dev, torch.float32).to(torch.complex64)
     d = I.random_complex_torch((nt, h, h), wl["seed"] + 200, dev, torch.complex64)
     torch.cuda.synchronize()
+
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ms, wall_ms, d64, u64 = time_pairs(plan, u, d, args.steps, args.warmup)
     log(f"[bench] c64 pair {ms:.3f} ms (host wall {wall_ms:.3f} ms)")
@@ -192,8 +227,8 @@ def main():
     bytes_launch = kernel_units(dom, plan, 8, 8, plan_slab)
     ach = bytes_launch / (kern[dom]["avg_launch_ms"] * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bytes_launch,
-            "avg_launch_ms": kern[dom]["avg_launch_ms"]}
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dom, plan_slab),
+            "bytes_per_launch": bytes_launch, "avg_launch_ms": kern[dom]["avg_launch_ms"]}
 
     result = {
         "metric": "lam fwd+adj pairs/s at 512^3 (c64 vs FP64, rel err <=1e-4); % HBM roofline",
