@@ -255,16 +255,11 @@ int build(lam_plan_s* P) {
   col_cfg(ilog2(p.h), p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
   c.g_log2TS = ilog2(TS);
   // gather: the tile plus its (2m-1) halo; scatter: two FP64 planes of the tile (pitch TS + 8)
-  // plus one record of 2 (2m) + 2 values of T and a corner per thread
   const size_t Pt = TS + 2 * m - 1;
   c.g_threads = 256;
   c.g_lds = (Pt * Pt + (Pt * Pt & 1)) * P->csize;
-  const size_t planes = 2 * (size_t)TS * (TS + 8) * sizeof(double);
-  const size_t RS = 2 * 2 * (size_t)m + 2;
-  auto s_bytes = [&](size_t nthr) { return planes + nthr * RS * P->rsize + nthr * sizeof(int) + 28 * sizeof(int); };
-  c.s_threads = 1024;
-  while (c.s_threads > 64 && s_bytes(c.s_threads) > kLdsMax) c.s_threads /= 2;
-  c.s_lds = s_bytes(c.s_threads);
+  c.s_threads = 512;
+  c.s_lds = 2 * (size_t)TS * (TS + 8) * sizeof(double);
   if (c.g_lds > kLdsMax || c.s_lds > kLdsMax) return fail(LAM_ERR_ARG, "tile kernels do not fit the LDS");
   return LAM_OK;
 }
@@ -393,10 +388,10 @@ int build_lists(lam_plan_s* P) {
     }
     std::stable_sort(gp, gp + ntiles, [&](int a, int b) { return work[a] > work[b]; });
     for (int i = 0; i < ntiles; ++i) {
-      int b[13], en[13];
-      const int nr = spread_ranges(of, P->ntx, P->nty, i / P->ntx, i % P->ntx, b, en);
+      int b[kSpreadSlots], en[kSpreadSlots];
+      spread_ranges(of, P->ntx, P->nty, i / P->ntx, i % P->ntx, b, en);
       work[i] = 0;
-      for (int j = 0; j < nr; ++j) work[i] += en[j] - b[j];
+      for (int j = 0; j < kSpreadSlots; ++j) work[i] += en[j] - b[j];
     }
     std::stable_sort(sp, sp + ntiles, [&](int a, int b) { return work[a] > work[b]; });
   }

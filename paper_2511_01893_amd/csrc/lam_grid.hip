@@ -10,16 +10,12 @@
 // listed exactly once (checked on the host: every slice holds n_theta w
 // entries).
 //   k_gather   stages a tile plus its (2m-1) halo in LDS and walks the tile's
-//              list: FP64 coordinates and weights, 2m x 2m FMA gather,
-//              optional fused "- d^" (Algorithm 2).
+//              list, one lane per target: FP64 coordinates, weights, 2m x 2m
+//              FMA gather, optional fused "- d^" (Algorithm 2).
 //   k_scatter  accumulates one tile in LDS in FP64: its own list plus the
 //              border classes of the 8 neighbouring tiles whose stencils
-//              reach in.  Phase 1 turns a round of targets into records
-//              (weights, sample, stencil corner); phase 2 gives every
-//              stencil tap of a record its own lane, so the 2m x 2m adds of a
-//              target hit distinct cells in distinct banks (native
-//              ds_add_f64; gfx950 runs FP64 LDS atomics ~20x faster than
-//              FP32 ones).  Every cell of the tile is then written once.
+//              reach in, one lane per stencil column, one FP64 LDS atomic per
+//              stencil row.  Every cell of the tile is then written once.
 #include "lam_internal.hpp"
 
 namespace lam {
@@ -77,7 +73,10 @@ __device__ __forceinline__ int border_class(int o, int TS, int MH) {
 }
 
 // Visit every target of slice k whose base row lies in the band of tile row
-// ty; calls f(t, aku, tx, class) with its tile column and border class.
+// ty.  One wave per angle; its lanes take consecutive k_u, so each call of
+// f(ok, t, aku, tx, class) (made by all lanes of the wave together; ok
+// marks the lanes holding a target of the band, tx its tile column) sees a
+// run of neighbouring targets along one line of the slice.
 template <int MH, class F>
 __device__ __forceinline__ void band_targets(const Dims& D, const double* cth, const double* sth, const double* line,
                                              int k, int ty, int log2TS, F&& f) {
@@ -85,19 +84,26 @@ __device__ __forceinline__ void band_targets(const Dims& D, const double* cth, c
   const int Y0 = ty * TS;
   const int kmin = -D.w / 2, kmax = D.w / 2 - 1;
   const double kv = (double)(k - D.h / 2) * D.xy.inv_h;
-  for (int t = threadIdx.x; t < D.ntheta; t += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  for (int t = wave; t < D.ntheta; t += nwave) {
     const double* ln = line + 6 * t;
     int lo[2], hi[2];
     const int n = axis_intervals(ln[3], ln[4], ln[5] * kv, Y0, TS, M1, kmin, kmax, lo, hi);
-    for (int j = 0; j < n; ++j)
-      for (int ku = lo[j]; ku <= hi[j]; ++ku) {
-        double sx, sy;
-        target_coords(D.xy, cth[t], sth[t], k, ku + D.w / 2, sx, sy);
-        const int oy = ((int)floor(sy) - Y0) & (M1 - 1);
-        if (oy >= TS) continue;
-        const int fx = (int)floor(sx) & (M2 - 1);
-        const int tx = fx >> log2TS, ox = fx & (TS - 1);
-        f(t, ku + D.w / 2, tx, border_class(oy, TS, MH) * 3 + border_class(ox, TS, MH));
+    for (int jj = 0; jj < n; ++jj)
+      for (int ku0 = lo[jj]; ku0 <= hi[jj]; ku0 += 64) {
+        const int ku = ku0 + lane;
+        bool ok = ku <= hi[jj];
+        int tx = 0, c = 0;
+        if (ok) {
+          double sx, sy;
+          target_coords(D.xy, cth[t], sth[t], k, ku + D.w / 2, sx, sy);
+          const int oy = ((int)floor(sy) - Y0) & (M1 - 1);
+          const int fx = (int)floor(sx) & (M2 - 1);
+          ok = oy < TS;
+          tx = fx >> log2TS;
+          c = border_class(oy, TS, MH) * 3 + border_class(fx & (TS - 1), TS, MH);
+        }
+        f(ok, t, ku + D.w / 2, tx, c);
       }
   }
 }
@@ -110,15 +116,19 @@ __global__ __launch_bounds__(256) void k_list_count(Dims D, Tables<T> tb, int lo
   int* cnt = reinterpret_cast<int*>(lam_smem);                 // [ntx * 9]
   for (int i = threadIdx.x; i < ntx * 9; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
-  band_targets<MH>(D, tb.cth, tb.sth, tb.line, k, ty, log2TS,
-                   [&](int, int, int tx, int c) { atomicAdd(&cnt[tx * 9 + c], 1); });
+  band_targets<MH>(D, tb.cth, tb.sth, tb.line, k, ty, log2TS, [&](bool ok, int, int, int tx, int c) {
+    if (ok) atomicAdd(&cnt[tx * 9 + c], 1);
+  });
   __syncthreads();
   const size_t per_slice = (size_t)ntx * nty * 9 + 1;
   int* out = counts + (size_t)k * per_slice + (size_t)ty * ntx * 9;
   for (int i = threadIdx.x; i < ntx * 9; i += blockDim.x) out[i] = cnt[i];
 }
 
-// lists[k][offset] = t * 4096 + aku, placed from the per-slice offsets
+// lists[k][offset] = t * 4096 + aku, placed from the per-slice offsets.  The
+// lanes of a wave that share a (tile, class) list take one contiguous block
+// of it in lane order, so each list holds runs of targets that are
+// neighbours along a line (the gather's LDS reads of a run overlap).
 template <typename T, int MH>
 __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log2TS, int k0, const int* __restrict__ offs,
                                                    int* __restrict__ lists) {
@@ -130,13 +140,71 @@ __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log
   for (int i = threadIdx.x; i < ntx * 9; i += blockDim.x) cur[i] = of[i];
   __syncthreads();
   int* L = lists + (size_t)k * D.ntheta * D.w;
-  band_targets<MH>(D, tb.cth, tb.sth, tb.line, k, ty, log2TS, [&](int t, int aku, int tx, int c) {
-    const int pos = atomicAdd(&cur[tx * 9 + c], 1);
-    L[pos] = t * 4096 + aku;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  band_targets<MH>(D, tb.cth, tb.sth, tb.line, k, ty, log2TS, [&](bool ok, int t, int aku, int tx, int c) {
+    const int dest = tx * 9 + c;
+    unsigned long long pending = __ballot(ok);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int d = __shfl(dest, leader);
+      const bool mine = ok && dest == d;
+      const unsigned long long m = __ballot(mine);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&cur[d], __popcll(m));
+      base = __shfl(base, leader);
+      if (mine) L[base + __popcll(m & below)] = t * 4096 + aku;
+      pending &= ~m;
+    }
   });
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Lane layout of the spread: a wave takes NG = 64 / GW targets
+// at a time, GW = the stencil width 2m rounded up to a power of two; lane j of
+// a target's group owns stencil column j, so one stencil row is GW adjacent
+// cells of the tile.  Every lane computes its target's FP64 coordinates, the
+// 2m y-weights and its own x-weight.
+// ---------------------------------------------------------------------------
+template <int MH> constexpr int group_width() { return 2 * MH <= 2 ? 2 : (2 * MH <= 4 ? 4 : (2 * MH <= 8 ? 8 : 16)); }
+
+// The weights exp(-beta (delta - o)^2), o = -m+1 .. m, are evaluated directly:
+// in FP32 for complex64 (the fractional offset delta is taken from the FP64
+// coordinate, so only the exponential is single precision) and in FP64 for
+// complex128.  The gather and the spread call the same code, so they stay an
+// exact adjoint pair.
+template <typename T, int MH>
+__device__ __forceinline__ void lane_stencil(double sx, double sy, double beta, int j, int& bx, int& by, T* wy,
+                                             T& wxj) {
+  const double fy = floor(sy), fx = floor(sx);
+  by = (int)fy;
+  bx = (int)fx;
+  const T dy = (T)(sy - fy), dx = (T)(sx - fx), b = (T)beta;
+#pragma unroll
+  for (int i = 0; i < 2 * MH; ++i) {
+    const T a = dy - (T)(i + 1 - MH);
+    wy[i] = exp(-b * a * a);
+  }
+  const T a = dx - (T)(j + 1 - MH);
+  wxj = j < 2 * MH ? exp(-b * a * a) : (T)0;
+}
+
+// All 2m weights along both axes (the gather's one-lane-per-target form).
+template <typename T, int MH>
+__device__ __forceinline__ void full_stencil(double sx, double sy, double beta, int& bx, int& by, T* wx, T* wy) {
+  const double fy = floor(sy), fx = floor(sx);
+  by = (int)fy;
+  bx = (int)fx;
+  const T dy = (T)(sy - fy), dx = (T)(sx - fx), b = (T)beta;
+#pragma unroll
+  for (int i = 0; i < 2 * MH; ++i) {
+    const T ay = dy - (T)(i + 1 - MH), ax = dx - (T)(i + 1 - MH);
+    wy[i] = exp(-b * ay * ay);
+    wx[i] = exp(-b * ax * ax);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // F_u2D gather over one tile of the oversampled grid
@@ -177,6 +245,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
   const int* of = tb.toff + (size_t)k * per_slice + (size_t)(ty * ntx + tx) * 9;
   const int beg = of[0], end = of[9];
   const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
+  // one lane per target; consecutive lanes take neighbouring targets of a run along a line
   for (int i = beg + tid; i < end; i += nth) {
     const int p = L[i];
     const int t = p >> 12, aku = p & 4095;
@@ -184,8 +253,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
     target_coords(D.xy, tb.cth[t], tb.sth[t], k, aku, sx, sy);
     T wx[W], wy[W];
     int bx, by;
-    stencil_weights<T, MH>(sx, D.beta, tb.rc, bx, wx);
-    stencil_weights<T, MH>(sy, D.beta, tb.rc, by, wy);
+    full_stencil<T, MH>(sx, sy, D.beta, bx, by, wx, wy);
     const int ox = (bx - x0) & (M2 - 1), oy = (by - y0) & (M1 - 1);
     T ax = 0, ay = 0;
 #pragma unroll
@@ -194,9 +262,9 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
       T rx = 0, ry = 0;
 #pragma unroll
       for (int ix = 0; ix < W; ++ix) {
-        const cpx<T> g = row[ix];
-        rx += wx[ix] * g.x;
-        ry += wx[ix] * g.y;
+        const cpx<T> v = row[ix];
+        rx += wx[ix] * v.x;
+        ry += wx[ix] * v.y;
       }
       ax += wy[iy] * rx;
       ay += wy[iy] * ry;
@@ -212,85 +280,83 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
 }
 
 // ---------------------------------------------------------------------------
-// F*_u2D spread into one tile of the oversampled grid
+// F*_u2D spread into one tile of the oversampled grid.  Each lane adds its
+// column's 2m taps, one stencil row per FP64 LDS atomic (native ds_add_f64;
+// gfx950 runs FP64 LDS atomics ~20x faster than FP32 ones); a wave's 64 adds
+// cover NG targets' rows, GW adjacent cells each.
 // ---------------------------------------------------------------------------
 template <typename T, int MH>
-__global__ __launch_bounds__(1024) void k_scatter(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ Gb, int k0,
-                                                  Dims D, Tables<T> tb, int log2TS) {
-  constexpr int W = 2 * MH;
-  constexpr int TPL = (W * W + 63) / 64;     // stencil taps per lane
-  constexpr int RS = 2 * W + 2;              // record: wy[W], wx[W], sample (re, im)
-  const int TS = 1 << log2TS, PA = TS + 8;   // PA = 8 (mod 32): 2 rows of 8 FP64 cells fill 32 banks
+__global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ Gb, int k0,
+                                                 Dims D, Tables<T> tb, int log2TS) {
+  constexpr int W = 2 * MH, GW = group_width<MH>(), NG = 64 / GW;
+  const int TS = 1 << log2TS, PA = TS + 8;   // PA = 8 (mod 32): stencil rows of a target fall in distinct banks
   const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
   const int ntx = M2 >> log2TS, nty = M1 >> log2TS;
-  const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+  const int tid = threadIdx.x, nth = blockDim.x;
   double* are = reinterpret_cast<double*>(lam_smem);           // [TS][PA]
   double* aim = are + TS * PA;                                  // [TS][PA]
-  T* rec = reinterpret_cast<T*>(aim + TS * PA);                 // [nth][RS]
-  int* corner = reinterpret_cast<int*>(rec + (size_t)nth * RS); // [nth]
-  int* rng = corner + nth;                                      // [2][14]: starts, prefix counts
   // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
   const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
-  const int tile = tb.sperm[(size_t)k * ntx * nty + rank];
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int tix = tb.sperm[(size_t)k * ntx * nty + rank];
+  const int tx = tix % ntx, ty = tix / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
   for (int e = tid; e < 2 * TS * PA; e += nth) are[e] = 0.0;
-  const size_t per_slice = (size_t)ntx * nty * 9 + 1;
-  const int* of = tb.toff + (size_t)k * per_slice;
-  if (tid == 0) {
-    int b[13], e[13];
-    const int nr = spread_ranges(of, ntx, nty, ty, tx, b, e);
-    int tot = 0;
-    for (int j = 0; j < nr; ++j) { rng[j] = b[j]; rng[14 + j] = tot; tot += e[j] - b[j]; }
-    rng[14 + nr] = tot;
-    rng[13] = nr;
-  }
-  __syncthreads();
-  const int nr = rng[13], total = rng[14 + nr];
-  const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
-  for (int r0 = 0; r0 < total; r0 += nth) {
-    // phase 1: one record per target
-    const int i = r0 + tid;
-    if (i < total) {
-      int j = 0;
-      while (j + 1 < nr && rng[14 + j + 1] <= i) ++j;
-      const int p = L[rng[j] + (i - rng[14 + j])];
-      const int t = p >> 12, aku = p & 4095;
-      double sx, sy;
-      target_coords(D.xy, tb.cth[t], tb.sth[t], k, aku, sx, sy);
-      T* rr = rec + (size_t)tid * RS;
-      int bx, by;
-      stencil_weights<T, MH>(sy, D.beta, tb.rc, by, rr);
-      stencil_weights<T, MH>(sx, D.beta, tb.rc, bx, rr + W);
-      const cpx<T> v = in[((size_t)t * D.h + k) * D.w + aku];
-      rr[2 * W] = v.x;
-      rr[2 * W + 1] = v.y;
-      corner[tid] = (((by - MH + 1 - y0) & (M1 - 1)) << 16) | ((bx - MH + 1 - x0) & (M2 - 1));
-    }
-    __syncthreads();
-    // phase 2: one lane per stencil tap
-    const int nrec = min(nth, total - r0);
-    for (int q = wave; q < nrec; q += nwave) {
-      const int c = corner[q];
-      const int ry0 = c >> 16, rx0 = c & 0xffff;
-      const T* rr = rec + (size_t)q * RS;
-      const T vx = rr[2 * W], vy = rr[2 * W + 1];
+  // the tile's list ranges (uniform over the block): fixed slots and their prefix counts
+  int rb[kSpreadSlots], re[kSpreadSlots], pre[kSpreadSlots + 1];
+  spread_ranges(tb.toff + (size_t)k * ((size_t)ntx * nty * 9 + 1), ntx, nty, ty, tx, rb, re);
+  pre[0] = 0;
 #pragma unroll
-      for (int kt = 0; kt < TPL; ++kt) {
-        const int tap = lane + 64 * kt;
-        if (tap < W * W) {
-          const int iy = tap / W, ix = tap - iy * W;
-          const int row = (ry0 + iy) & (M1 - 1), col = (rx0 + ix) & (M2 - 1);
-          if (row < TS && col < TS) {
-            const T w = rr[iy] * rr[W + ix];
-            atomicAdd(are + row * PA + col, (double)(w * vx));
-            atomicAdd(aim + row * PA + col, (double)(w * vy));
-          }
+  for (int q = 0; q < kSpreadSlots; ++q) pre[q + 1] = pre[q] + (re[q] - rb[q]);
+  const int total = pre[kSpreadSlots];
+  const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+  const int g = lane / GW, j = lane & (GW - 1);
+  __syncthreads();
+  // the NG targets of a wave step come from NG far-apart stretches of the list (the lists hold runs of
+  // neighbouring targets, whose stencils overlap: adds to one cell within an instruction serialise)
+  const int stretch = (total + NG - 1) / NG;
+  // list entry of wave step i0 for this lane's group, -1 past the end: the last slot starting at or
+  // before i holds it (empty slots share their successor's start)
+  auto entry = [&](int i0) {
+    const int i = g * stretch + i0;
+    int idx = rb[0] + i;
+#pragma unroll
+    for (int q = 1; q < kSpreadSlots; ++q)
+      if (i >= pre[q]) idx = rb[q] + (i - pre[q]);
+    return (i0 < stretch && i < total) ? L[idx] : -1;
+  };
+  // two-stage software pipeline: while step n adds, the sample and angle of step n + 1 and the list
+  // entry of step n + 2 are in flight
+  int pA = entry(wave), pB = entry(wave + nwave);
+  int tA = max(pA, 0) >> 12, uA = max(pA, 0) & 4095;
+  double cA = tb.cth[tA], sA = tb.sth[tA];
+  cpx<T> vA = in[((size_t)tA * D.h + k) * D.w + uA];
+  for (int i0 = wave; i0 < stretch; i0 += nwave) {
+    const int pC = entry(i0 + 2 * nwave);
+    const int tB = max(pB, 0) >> 12, uB = max(pB, 0) & 4095;
+    const double cB = tb.cth[tB], sB = tb.sth[tB];
+    const cpx<T> vB = in[((size_t)tB * D.h + k) * D.w + uB];
+    double sx, sy;
+    target_coords(D.xy, cA, sA, k, uA, sx, sy);
+    T wy[W], wxj;
+    int bx, by;
+    lane_stencil<T, MH>(sx, sy, D.beta, j, bx, by, wy, wxj);
+    const int col = (bx - MH + 1 + j - x0) & (M2 - 1);
+    if (pA >= 0 && j < W && col < TS) {
+      const T vx = wxj * vA.x, vy = wxj * vA.y;
+#pragma unroll
+      for (int iy = 0; iy < W; ++iy) {
+        const int row = (by - MH + 1 + iy - y0) & (M1 - 1);
+        if (row < TS) {
+          atomicAdd(are + row * PA + col, (double)(wy[iy] * vx));
+          atomicAdd(aim + row * PA + col, (double)(wy[iy] * vy));
         }
       }
     }
-    __syncthreads();
+    pA = pB; tA = tB; uA = uB; cA = cB; sA = sB; vA = vB;
+    pB = pC;
   }
+  __syncthreads();
   cpx<T>* G = Gb + (size_t)kk * M1 * M2;
   for (int e = tid; e < TS * TS; e += nth) {
     const int r = e >> log2TS, c = e & (TS - 1);

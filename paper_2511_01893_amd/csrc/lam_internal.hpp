@@ -38,32 +38,37 @@ struct Tables {
 };
 
 // The list ranges [b, e) of one slice that tile (ty, tx) consumes in the adjoint
-// spread: its own list (all border classes), then the border classes of the
-// neighbouring tiles whose stencils reach into it (the facing column of a left /
-// right neighbour, the facing row of an upper / lower one, the facing corner of
-// a diagonal one).  of: the slice's [n_tiles 9 + 1] offsets.  Returns the number
-// of non-empty ranges (at most 13).
-__host__ __device__ inline int spread_ranges(const int* of, int ntx, int nty, int ty, int tx, int* b, int* e) {
-  int nr = 0;
-  auto add = [&](int tyy, int txx, int c0, int c1) {
+// spread, in 13 fixed slots (empty where a slot does not apply): its own list
+// (all border classes); the facing border column of the left and right
+// neighbours (3 classes each); the facing border row of the upper and lower
+// neighbours; the facing corner of the 4 diagonal neighbours.  Neighbours along
+// an axis with a single tile are skipped.  of: the slice's [n_tiles 9 + 1]
+// offsets.  Fixed slots keep the arrays in registers on the device.
+constexpr int kSpreadSlots = 13;
+__host__ __device__ inline void spread_ranges(const int* of, int ntx, int nty, int ty, int tx, int* b, int* e) {
+  auto set = [&](int slot, int tyy, int txx, int c0, int c1) {
     const int* o = of + (tyy * ntx + txx) * 9;
-    if (o[c1] > o[c0]) { b[nr] = o[c0]; e[nr] = o[c1]; ++nr; }
+    b[slot] = o[c0];
+    e[slot] = o[c1];
   };
-  add(ty, tx, 0, 9);
-  for (int dy = -1; dy <= 1; ++dy)
-    for (int dx = -1; dx <= 1; ++dx) {
-      if ((dx == 0 && dy == 0) || (dx != 0 && ntx == 1) || (dy != 0 && nty == 1)) continue;
-      const int ny_ = (ty + dy + nty) % nty, nx_ = (tx + dx + ntx) % ntx;
-      const int cx = dx < 0 ? 2 : 0, cy = dy < 0 ? 2 : 0;     // the neighbour's border facing this tile
-      if (dy == 0) {
-        for (int c = 0; c < 3; ++c) add(ny_, nx_, 3 * c + cx, 3 * c + cx + 1);
-      } else if (dx == 0) {
-        add(ny_, nx_, 3 * cy, 3 * cy + 3);
-      } else {
-        add(ny_, nx_, 3 * cy + cx, 3 * cy + cx + 1);
-      }
+  for (int s = 0; s < kSpreadSlots; ++s) b[s] = e[s] = 0;
+  set(0, ty, tx, 0, 9);
+  const int xl = (tx + ntx - 1) % ntx, xr = (tx + 1) % ntx, yu = (ty + nty - 1) % nty, yd = (ty + 1) % nty;
+  if (ntx > 1)
+    for (int c = 0; c < 3; ++c) {
+      set(1 + c, ty, xl, 3 * c + 2, 3 * c + 3);    // left neighbour: its high-x border column
+      set(4 + c, ty, xr, 3 * c, 3 * c + 1);        // right neighbour: its low-x border column
     }
-  return nr;
+  if (nty > 1) {
+    set(7, yu, tx, 6, 9);                          // upper neighbour: its high-y border row
+    set(8, yd, tx, 0, 3);                          // lower neighbour: its low-y border row
+  }
+  if (ntx > 1 && nty > 1) {
+    set(9, yu, xl, 8, 9);
+    set(10, yu, xr, 6, 7);
+    set(11, yd, xl, 2, 3);
+    set(12, yd, xr, 0, 1);
+  }
 }
 
 // Launch shapes chosen by the host plan.
