@@ -251,37 +251,49 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
   const int* of = tb.toff + (size_t)k * per_slice + (size_t)(ty * ntx + tx) * 9;
   const int beg = of[0], end = of[9];
   const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
-  // one lane per target; consecutive lanes take neighbouring targets of a run along a line
-  for (int i = beg + tid; i < end; i += nth) {
-    const int p = L[i];
-    const int t = p >> 12, aku = p & 4095;
-    double sx, sy;
-    target_coords(D.xy, tb.cth[t], tb.sth[t], k, aku, sx, sy);
-    T wx[W], wy[W];
-    int bx, by;
-    full_stencil<T, MH>(sx, sy, D.beta, bx, by, wx, wy);
-    const int ox = (bx - x0) & (M2 - 1), oy = (by - y0) & (M1 - 1);
-    T ax = 0, ay = 0;
+  // one lane per target; consecutive lanes take neighbouring targets of a run along a line, and each
+  // lane takes UG targets per step whose loads are in flight together
+  constexpr int UG = 2;
+  for (int i0 = beg + tid; i0 < end; i0 += UG * nth) {
+    int t[UG], uk[UG];
+    double c[UG], sn[UG];
+    cpx<T> dd[UG];
 #pragma unroll
-    for (int iy = 0; iy < W; ++iy) {
-      const cpx<T>* row = tile + (oy + iy) * P + ox;
-      T rx = 0, ry = 0;
+    for (int u = 0; u < UG; ++u) {
+      const int pe = L[min(i0 + u * nth, end - 1)];
+      t[u] = pe >> 12;
+      uk[u] = pe & 4095;
+    }
 #pragma unroll
-      for (int ix = 0; ix < W; ++ix) {
-        const cpx<T> v = row[ix];
-        rx += wx[ix] * v.x;
-        ry += wx[ix] * v.y;
+    for (int u = 0; u < UG; ++u) {
+      c[u] = tb.cth[t[u]];
+      sn[u] = tb.sth[t[u]];
+      dd[u] = dhat ? dhat[((size_t)t[u] * D.h + k) * D.w + uk[u]] : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+      double sx, sy;
+      target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
+      T wx[W], wy[W];
+      int bx, by;
+      full_stencil<T, MH>(sx, sy, D.beta, bx, by, wx, wy);
+      const int ox = (bx - x0) & (M2 - 1), oy = (by - y0) & (M1 - 1);
+      T ax = 0, ay = 0;
+#pragma unroll
+      for (int iy = 0; iy < W; ++iy) {
+        const cpx<T>* row = tile + (oy + iy) * P + ox;
+        T rx = 0, ry = 0;
+#pragma unroll
+        for (int ix = 0; ix < W; ++ix) {
+          const cpx<T> v = row[ix];
+          rx += wx[ix] * v.x;
+          ry += wx[ix] * v.y;
+        }
+        ax += wy[iy] * rx;
+        ay += wy[iy] * ry;
       }
-      ax += wy[iy] * rx;
-      ay += wy[iy] * ry;
+      if (i0 + u * nth < end) out[((size_t)t[u] * D.h + k) * D.w + uk[u]] = mk(ax - dd[u].x, ay - dd[u].y);
     }
-    const size_t o = ((size_t)t * D.h + k) * D.w + aku;
-    if (dhat) {
-      const cpx<T> dd = dhat[o];
-      ax -= dd.x;
-      ay -= dd.y;
-    }
-    out[o] = mk(ax, ay);
   }
 }
 
@@ -324,7 +336,7 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   // targets of a wave step come from NG * U far-apart stretches of the positions (the lists hold
   // runs of neighbouring targets, whose stencils overlap, and adds to one cell within an
   // instruction serialise); the U targets of a lane group are independent load chains.
-  constexpr int U = 2;
+  constexpr int U = 4;
   auto spread = [&](int n, auto idx_of) {
     const int stretch = (n + NG * U - 1) / (NG * U);
     for (int i0 = wave; i0 < stretch; i0 += nwave) {
