@@ -330,8 +330,6 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
   const int g = lane / GW, j = lane & (GW - 1);
   __syncthreads();
-  // the NG targets of a wave step come from NG far-apart stretches of the list (the lists hold runs of
-  // neighbouring targets, whose stencils overlap: adds to one cell within an instruction serialise)
   // Add the targets of list positions [0, n) (position -> list index by idx_of): the NG * U
   // targets of a wave step come from NG * U far-apart stretches of the positions (the lists hold
   // runs of neighbouring targets, whose stencils overlap, and adds to one cell within an
