@@ -73,7 +73,8 @@ template <typename T, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
 // NB = 2^log2nb transforms.  Each radix-R stage reads every value into
 // registers, synchronises, applies twiddles and the R-point DFT and writes
 // the results to their autosorted positions, then synchronises again, so
-// one buffer suffices.  Values per thread per stage = N*NB/nthreads, which
+// one buffer suffices.  nth is the work-group size.  Values per thread per
+// stage = N*NB/nth, which
 // must not exceed VPT.  tw[t] = exp(-2 pi i t / 2^log2tw), 2^log2tw >= N,
 // generated in FP64 on the host and rounded to T.  bfast selects the thread
 // to (j, b) map: batch index fastest (for interleaved [p][b] layouts) or
@@ -87,10 +88,10 @@ template <bool PAD> __device__ __forceinline__ int lpad(int e) { return PAD ? e 
 
 template <typename T, int R, int VPT, bool PAD = false>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, int Ns, int log2span, int sp, int sb,
-                                          bool bfast, const cpx<T>* __restrict__ tw, int log2tw) {
+                                          bool bfast, const cpx<T>* __restrict__ tw, int log2tw, int nth) {
   constexpr int IT = VPT / R;
   constexpr int LR = (R == 8) ? 3 : (R == 4 ? 2 : 1);
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x;
   const int log2nbf = log2n - LR;                      // butterflies per transform = N / R
   const int total = 1 << (log2nbf + log2nb);
   const int nbf = 1 << log2nbf;
@@ -129,17 +130,17 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, in
 
 template <typename T, int VPT, bool PAD = false>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int log2n, int log2nb, int sp, int sb, bool bfast,
-                        const cpx<T>* __restrict__ tw, int log2tw) {
+                        const cpx<T>* __restrict__ tw, int log2tw, int nth) {
   int Ns = 1, lspan = 0, rem = log2n;
   while (rem > 0) {
     if (rem >= 3) {
-      fft_stage<T, 8, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 3, sp, sb, bfast, tw, log2tw);
+      fft_stage<T, 8, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 3, sp, sb, bfast, tw, log2tw, nth);
       Ns <<= 3; lspan += 3; rem -= 3;
     } else if (rem == 2) {
-      fft_stage<T, 4, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 2, sp, sb, bfast, tw, log2tw);
+      fft_stage<T, 4, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 2, sp, sb, bfast, tw, log2tw, nth);
       Ns <<= 2; lspan += 2; rem -= 2;
     } else {
-      fft_stage<T, 2, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw);
+      fft_stage<T, 2, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw, nth);
       Ns <<= 1; lspan += 1; rem -= 1;
     }
   }

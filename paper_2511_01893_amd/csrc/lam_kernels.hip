@@ -58,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < D.h * TX; e += nth) {
     const int av = e >> log2TX, b = e & (TX - 1);
     const int base = tb.zbase[av] - MH + 1;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     if (e < total) buf[e] = v[it];
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < n0 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     const cpx<T> g = buf[((a - n0 / 2) & (M0 - 1)) * TX + b];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M1, log2TX, TX, 1, true, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>()>(buf, D.log2M1, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < M1 * TX; e += nth) {
     const int q = e >> log2TX, b = e & (TX - 1);
     Tb[((size_t)kk * M1 + q) * n2 + x0 + b] = buf[e];
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M1, log2TX, TX, 1, true, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>()>(buf, D.log2M1, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < n1 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     const cpx<T> v = buf[((a - n1 / 2) & (M1 - 1)) * TX + b];
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < RB * M2; e += nth) Gb[r0 * M2 + e] = buf[lpad<true>(e)];
 }
 
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < RB * n2; e += nth) {
     const int b = e >> log2n2, a = e & (n2 - 1);
     Tb[(r0 + b) * n2 + a] = conj(buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))]);
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, 
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>(), true>(buf, log2L, log2RB, 1, L, false, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>(), true>(buf, log2L, log2RB, 1, L, false, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < RB * L; e += nth) {
     const cpx<T> v = buf[lpad<true>(e)];
     out[r0 * L + e] = inverse ? conj(v) : v;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, 
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, log2h, log2TX, TX, 1, true, tb.tw, tb.log2tw);
+  lds_fft<T, vpt<T>()>(buf, log2h, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
   for (int e = tid; e < H * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     cpx<T> v = buf[e];
