@@ -28,7 +28,7 @@
  *     deconvolution c(j) = sqrt(pi/tau) exp(tau j^2) / M.
  *
  * Memory.  Every array argument is a DEVICE pointer to a contiguous C-order
- * buffer owned by the caller.  Complex arrays are interleaved (re, im):
+ * buffer owned by the caller (the host-streamed pair takes host pointers).  Complex arrays are interleaved (re, im):
  * float pairs for LAM_C64, double pairs for LAM_C128.  Real arrays (the
  * *_real entry points and the ADMM state) are float for LAM_C64 and double
  * for LAM_C128.  The library never allocates device memory: scratch space is
@@ -81,8 +81,9 @@ typedef struct {
                             16 .. 4096                                              */
   int oversample;        /* R; must be 2                                            */
   int m;                 /* Gaussian half-width, 1 .. 8 (2m taps per axis)          */
-  lam_dtype dtype;       /* LAM_C64: complex64 data, FP32 accumulation, FP64
-                            coordinates/weights; LAM_C128: complex128 throughout    */
+  lam_dtype dtype;       /* LAM_C64: complex64 data, FP32 arithmetic, FP64
+                            coordinates, FP64 tables, 2D stencil weights as FP32
+                            exponentials; LAM_C128: complex128 throughout          */
   int slab;              /* k_v slices per internal slab of the 2D step; 0 = auto.
                             Bounds the oversampled-grid scratch to slab slices.     */
 } lam_params;
@@ -131,17 +132,21 @@ int lam_adj_hat(lam_plan p, const void* r, void* u, void* hip_stream);
 
 /* Host-streamed forward and adjoint for volumes and data that live in host
  * memory (the chunk pipeline the Background section describes for LSP, where
- * host-to-device chunk transfers overlap the FFT work).  u_host: pinned host array (n0, n1, n2), real (u_real != 0,
- * float/double per dtype) or complex; d_host: pinned host complex
- * (ntheta, h, w).  The volume moves in y-slabs through two staging buffers of
- * the workspace (F_u1D needs whole z columns), the data in theta-slabs through
- * the workspace's resident data buffer (F_2D needs whole projections); the
- * intermediate stage arrays stay in device memory.  Copies run on a stream the
- * plan owns, ordered against the caller's stream with events; the call
- * returns at once and the caller's stream is complete when the host arrays are.
- * lam_stream_slabs sets the slab sizes (volume rows per y-slab, at most the
- * staging capacity chosen at lam_init, about 64 MiB; projections per
- * theta-slab). */
+ * host-to-device chunk transfers overlap the FFT work).
+ *   u_host  host array (n0, n1, n2): real (u_real != 0; float or double per
+ *           dtype) or complex
+ *   d_host  host complex array (ntheta, h, w)
+ * Pinned memory lets the copies overlap the kernels; pageable memory is
+ * accepted (HIP stages those copies, which then do not overlap).  The volume
+ * moves in y-slabs through two staging buffers of the workspace (F_u1D needs
+ * whole z columns), the data in theta-slabs through the workspace's resident
+ * data buffer (F_2D needs whole projections); the intermediate stage arrays
+ * stay in device memory.  Copies run on a stream the plan owns, ordered
+ * against the caller's stream with events; the call returns at once and the
+ * host arrays are complete when the caller's stream is.  lam_stream_slabs
+ * sets the slab sizes (volume rows per y-slab, at most the staging capacity
+ * chosen at lam_init, about 64 MiB; projections per theta-slab).  Errors as
+ * for lam_fwd; LAM_ERR_ARG for null host pointers or slab sizes out of range. */
 int lam_fwd_streamed(lam_plan p, const void* u_host, int u_real, void* d_host, void* hip_stream);
 int lam_adj_streamed(lam_plan p, const void* d_host, void* u_host, int u_real, void* hip_stream);
 int lam_stream_slabs(lam_plan p, int y_rows, int theta_proj);

@@ -82,24 +82,27 @@ def _cube_layer(shape, cube_values: np.ndarray) -> np.ndarray:
     return lay
 
 
-def blob_phantom_torch(shape, blobs: BlobSet, device, dtype):
+def blob_phantom_torch(shape, blobs: BlobSet, device, dtype, z_range=None):
     """Same phantom evaluated with torch on ``device`` (float64 math, cast to ``dtype``).
 
     Used for large volumes, where the NumPy loop would take minutes.  The
-    arithmetic is the blob formula only."""
+    arithmetic is the blob formula only.  ``z_range=(z0, z1)`` returns only the
+    planes z0 <= z < z1 of the volume (for volumes that are built slab by slab)."""
     import torch
 
     n0, n1, n2 = shape
+    z0, z1 = (0, n0) if z_range is None else z_range
     ax = [torch.as_tensor(_axis(k), dtype=torch.float64, device=device) for k in (n0, n1, n2)]
     z, y, x = ax
-    u = torch.zeros(shape, dtype=torch.float64, device=device)
+    z = z[z0:z1]
+    u = torch.zeros((z1 - z0, n1, n2), dtype=torch.float64, device=device)
     for c, s, a in zip(blobs.centres, blobs.sigmas, blobs.amps):
         gx = torch.exp(-((x - float(c[0])) ** 2) / (2 * s * s))
         gy = torch.exp(-((y - float(c[1])) ** 2) / (2 * s * s))
         gz = float(a) * torch.exp(-((z - float(c[2])) ** 2) / (2 * s * s))
         u += gz[:, None, None] * (gy[:, None] * gx[None, :])[None, :, :]
     if blobs.cube_values is not None:
-        u += torch.as_tensor(_cube_layer(shape, blobs.cube_values), device=device)
+        u += torch.as_tensor(_cube_layer(shape, blobs.cube_values)[z0:z1], device=device)
     return u.to(dtype)
 
 

@@ -204,8 +204,10 @@ class Plan:
 
     # ---------------------------------------------------------------- host-streamed
     def _host(self, x: torch.Tensor, shape, what: str, allow_real=False) -> torch.Tensor:
-        if x.device.type != "cpu" or not x.is_pinned():
-            raise ValueError(f"{what}: expected a pinned host tensor (pin_memory=True)")
+        # pinned memory lets the slab copies overlap the kernels; pageable memory works too (HIP stages the
+        # copies), for arrays too large to pin
+        if x.device.type != "cpu":
+            raise ValueError(f"{what}: expected a host tensor")
         if tuple(x.shape) != tuple(shape):
             raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(x.shape)}")
         ok = (self.dtype,) + ((self.rdtype,) if allow_real else ())
@@ -220,7 +222,7 @@ class Plan:
         _check(lib().lam_stream_slabs(self._h, int(y_rows), int(theta_proj)))
 
     def fwd_streamed(self, u: torch.Tensor, out: torch.Tensor | None = None, wait: bool = True) -> torch.Tensor:
-        """d = L u with u and d in pinned host memory, slab copies overlapped with the kernels."""
+        """d = L u with u and d in host memory (pinned: slab copies overlapped with the kernels)."""
         self._host(u, self.vol_shape, "u", allow_real=True)
         out = torch.empty(self.data_shape, dtype=self.dtype, pin_memory=True) if out is None else out
         self._host(out, self.data_shape, "d")
@@ -232,7 +234,7 @@ class Plan:
 
     def adj_streamed(self, d: torch.Tensor, real: bool = False, out: torch.Tensor | None = None,
                      wait: bool = True) -> torch.Tensor:
-        """u = L* d (Re if real) with d and u in pinned host memory."""
+        """u = L* d (Re if real) with d and u in host memory (pinned: copies overlapped with the kernels)."""
         self._host(d, self.data_shape, "d")
         dt = self.rdtype if real else self.dtype
         out = torch.empty(self.vol_shape, dtype=dt, pin_memory=True) if out is None else out
