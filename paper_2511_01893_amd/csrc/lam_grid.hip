@@ -335,6 +335,8 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   // runs of neighbouring targets, whose stencils overlap, and adds to one cell within an
   // instruction serialise); the U targets of a lane group are independent load chains.
   constexpr int U = 4;
+  const size_t hw = (size_t)D.h * D.w;
+  const int kw = k * D.w;
   auto spread = [&](int n, auto idx_of) {
     const int stretch = (n + NG * U - 1) / (NG * U);
     for (int i0 = wave; i0 < stretch; i0 += nwave) {
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
       for (int u = 0; u < U; ++u) {
         c[u] = tb.cth[t[u]];
         sn[u] = tb.sth[t[u]];
-        v[u] = in[((size_t)t[u] * D.h + k) * D.w + uk[u]];
+        v[u] = in[(size_t)t[u] * hw + kw + uk[u]];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -365,13 +367,17 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
         lane_stencil<T, MH>(sx, sy, D.beta, j, bx, by, wy, wxj);
         const int col = (bx - MH + 1 + j - x0) & (M2 - 1);
         if (ok[u] && j < W && col < TS) {
-          const T vx = wxj * v[u].x, vy = wxj * v[u].y;
+          // FP64 products of the FP32 weights and samples: one conversion per weight, not per add
+          const double vx = (double)(wxj * v[u].x), vy = (double)(wxj * v[u].y);
+          const int r0 = by - MH + 1 - y0;
 #pragma unroll
           for (int iy = 0; iy < W; ++iy) {
-            const int row = (by - MH + 1 + iy - y0) & (M1 - 1);
+            const int row = (r0 + iy) & (M1 - 1);
             if (row < TS) {
-              atomicAdd(are + row * PA + col, (double)(wy[iy] * vx));
-              atomicAdd(aim + row * PA + col, (double)(wy[iy] * vy));
+              const int a = __umul24(row, PA) + col;
+              const double w = (double)wy[iy];
+              atomicAdd(are + a, w * vx);
+              atomicAdd(aim + a, w * vy);
             }
           }
         }

@@ -72,13 +72,15 @@ def test_streamed_ordering_on_a_side_stream(L):
         assert torch.equal(o, r)
 
 
-def test_streamed_argument_errors(L):
+def test_streamed_pageable_and_argument_errors(L):
     plan = L.Plan(32, ntheta=16, phi=math.radians(20))
-    u = torch.zeros(plan.vol_shape)
-    with pytest.raises(ValueError):
-        plan.fwd_streamed(u)                                  # not pinned
+    u = I.blob_phantom_torch(plan.vol_shape, I.draw_blobs(9, 4), "cpu", torch.float32)
+    # pageable host memory is accepted (the copies are staged by HIP and do not overlap)
+    assert torch.equal(plan.fwd_streamed(u), plan.fwd(u.cuda()).cpu())
     with pytest.raises(ValueError):
         plan.fwd_streamed(u.cuda())                           # device tensor
+    with pytest.raises(ValueError):
+        plan.fwd_streamed(u.double())                         # wrong dtype
     with pytest.raises(L.LamError):
         plan.stream_slabs(0, 4)
     with pytest.raises(L.LamError):
