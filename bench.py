@@ -77,12 +77,13 @@ def time_pairs(plan, u, d, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall, out_d, out_u
 
 
-def cpu_baseline(wl, budget_slices=4):
+def cpu_baseline(wl, budget_slices=16, col_fraction=16, nproj=32):
     """Time the FP64 oracle on a bounded sample of one pair and scale to pairs/s.
 
-    Sample: F_u1D / F*_u1D on 1/64 of the (y, x) columns, F_u2D / F*_u2D on
-    `budget_slices` k_v slices, F*_2D / F_2D on 8 projections; each part is
-    scaled by (total units / sampled units)."""
+    Sample (about 10 s of CPU work at 512^3): F_u1D / F*_u1D on 1/col_fraction
+    of the (y, x) columns, F_u2D / F*_u2D on `budget_slices` k_v slices, F*_2D /
+    F_2D on `nproj` projections; each part is scaled by (total units / sampled
+    units)."""
     import numpy as np
 
     from oracle import lam_oracle as O
@@ -94,7 +95,7 @@ def cpu_baseline(wl, budget_slices=4):
     def cplx(*shape):
         return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
-    ncol = n * n // 64
+    ncol = n * n // col_fraction
     _, _, nu_z = O.frequencies(g)
     x = cplx(n, ncol)
     t = time.perf_counter(); f = O.usfft1d_fwd(x, n * nu_z, 2, 4); t_z = time.perf_counter() - t
@@ -105,10 +106,10 @@ def cpu_baseline(wl, budget_slices=4):
         u1[k] = cplx(n, n)
     t = time.perf_counter(); r = O.fu2d(u1, g, kv_list=sl); t_2 = time.perf_counter() - t
     t = time.perf_counter(); O.fu2d_adj(r, g, kv_list=sl); t_2a = time.perf_counter() - t
-    p8 = cplx(8, h, h)
-    t = time.perf_counter(); O.f2d_inv(p8); t_f = time.perf_counter() - t
-    t = time.perf_counter(); O.f2d(p8); t_fa = time.perf_counter() - t
-    per_pair = ((t_z + t_za) * 64 + (t_2 + t_2a) * h / len(sl) + (t_f + t_fa) * nt / 8)
+    pp = cplx(nproj, h, h)
+    t = time.perf_counter(); O.f2d_inv(pp); t_f = time.perf_counter() - t
+    t = time.perf_counter(); O.f2d(pp); t_fa = time.perf_counter() - t
+    per_pair = ((t_z + t_za) * col_fraction + (t_2 + t_2a) * h / len(sl) + (t_f + t_fa) * nt / nproj)
     sample_s = t_z + t_za + t_2 + t_2a + t_f + t_fa
     return {
         "value": 1.0 / per_pair,
@@ -116,7 +117,7 @@ def cpu_baseline(wl, budget_slices=4):
         "cores": O.WORKERS,
         "kind": "oracle",
         "sample": (f"F_u1D+adj on {ncol} of {n * n} columns, F_u2D+adj on {len(sl)} of {h} slices, "
-                   f"F*_2D+F_2D on 8 of {nt} projections; {sample_s:.1f} s of CPU time, scaled"),
+                   f"F*_2D+F_2D on {nproj} of {nt} projections; {sample_s:.1f} s of CPU time, scaled"),
         "seconds_per_pair": per_pair,
     }
 
