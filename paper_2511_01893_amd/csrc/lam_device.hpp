@@ -117,8 +117,22 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, in
       if (bfast) { b = t & ((1 << log2nb) - 1); j = t >> log2nb; }
       else { j = t & (nbf - 1); b = t >> log2nbf; }
       const int k = j & (Ns - 1);
+      // the R-1 twiddles w^r, w = exp(-2 pi i k / span): w and w^4 from the FP64-built table, the rest
+      // by at most two complex products (two table loads per radix-8 butterfly instead of seven)
+      cpx<T> tw_r[R];
+      tw_r[1] = tw[k << twsh];
+      if constexpr (R >= 4) {
+        tw_r[2] = cmul(tw_r[1], tw_r[1]);
+        tw_r[3] = cmul(tw_r[2], tw_r[1]);
+      }
+      if constexpr (R == 8) {
+        tw_r[4] = tw[(4 * k) << twsh];
+        tw_r[5] = cmul(tw_r[4], tw_r[1]);
+        tw_r[6] = cmul(tw_r[4], tw_r[2]);
+        tw_r[7] = cmul(tw_r[4], tw_r[3]);
+      }
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[(r * k) << twsh]);
+      for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw_r[r]);
       dftR<T, R>(v[it]);
       const int idxD = (j - k) * R + k;
 #pragma unroll
