@@ -45,12 +45,12 @@ struct lam_plan_s {
   double beta = 0;
   size_t csize = 8, rsize = 4;
   // host tables (FP64)
-  std::vector<double> tw, cz, cy, cx, zw, cth, sth, rc, line;
-  std::vector<int> zbase, zq_ptr, zq_av;
-  std::vector<double> zq_w;
+  std::vector<double> tw, cz, cy, cx, zdelta, cth, sth, rc, line;
+  std::vector<int> zbase;
+  std::vector<unsigned> zrun;
   // workspace layout (byte offsets)
-  size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zw = 0, off_cth = 0, off_sth = 0,
-         off_rc = 0, off_line = 0, off_zq_ptr = 0, off_zq_av = 0, off_zq_w = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
+  size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zdelta = 0, off_cth = 0, off_sth = 0,
+         off_rc = 0, off_line = 0, off_zrun = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   int ntx = 1, nty = 1;        // tiles of the oversampled grid per slice
@@ -129,34 +129,36 @@ int build(lam_plan_s* P) {
   P->cz = deconv(p.n0, R, m);
   P->cy = deconv(p.n1, R, m);
   P->cx = deconv(p.n2, R, m);
-  // z-gather: targets xi_z = n0 (k_v / h) cos(phi), s = R xi_z
+  // z-gather: targets xi_z = n0 (k_v / h) cos(phi), s = R xi_z; per detector row the stencil base
+  // floor(s) and the fractional offset (the kernels evaluate the weights from it)
   P->zbase.resize(p.h);
-  P->zw.resize((size_t)p.h * 2 * m);
+  P->zdelta.resize(p.h);
   for (int av = 0; av < p.h; ++av) {
     const double kv = (double)(av - p.h / 2) / (double)p.h;
     const double s = R * (p.n0 * (kv * std::cos(p.phi)));
-    const double b = std::floor(s), d = s - b;
+    const double b = std::floor(s);
     P->zbase[av] = (int)b;
-    for (int i = 0; i < 2 * m; ++i) {
-      const double o = (double)(i - m + 1);
-      P->zw[(size_t)av * 2 * m + i] = std::exp(-P->beta * (d - o) * (d - o));
-    }
+    P->zdelta[av] = s - b;
   }
-  // inverse z table: for each oversampled grid point q, the (k_v, weight)
-  // pairs whose stencil covers q (the adjoint's gather form)
+  // inverse z map for the adjoint's gather form: for each oversampled grid point q, the detector
+  // rows whose stencil covers q.  The bases grow with the row, so these rows form one run (two when
+  // the stencils of the first rows wrap around the periodic grid); packed as start | count << 16.
   {
-    std::vector<std::vector<std::pair<int, double>>> rows(P->M0);
+    std::vector<std::vector<int>> rows(P->M0);
     for (int av = 0; av < p.h; ++av)
-      for (int i = 0; i < 2 * m; ++i) {
-        const int q = (P->zbase[av] - m + 1 + i) & (P->M0 - 1);
-        rows[q].emplace_back(av, P->zw[(size_t)av * 2 * m + i]);
-      }
-    P->zq_ptr.assign(P->M0 + 1, 0);
-    P->zq_av.clear();
-    P->zq_w.clear();
+      for (int i = 0; i < 2 * m; ++i) rows[(P->zbase[av] - m + 1 + i) & (P->M0 - 1)].push_back(av);
+    P->zrun.assign(2 * (size_t)P->M0, 0u);
     for (int q = 0; q < P->M0; ++q) {
-      for (auto& e : rows[q]) { P->zq_av.push_back(e.first); P->zq_w.push_back(e.second); }
-      P->zq_ptr[q + 1] = (int)P->zq_av.size();
+      std::vector<int>& r = rows[q];
+      std::sort(r.begin(), r.end());
+      int nrun = 0;
+      for (size_t a = 0; a < r.size();) {
+        size_t e = a + 1;
+        while (e < r.size() && r[e] == r[e - 1] + 1) ++e;
+        if (nrun == 2) return fail(LAM_ERR_ARG, "z stencil map has more than two runs per grid point");
+        P->zrun[2 * (size_t)q + nrun++] = (unsigned)r[a] | ((unsigned)(e - a) << 16);
+        a = e;
+      }
     }
   }
   P->cth.resize(p.ntheta);
@@ -198,14 +200,12 @@ int build(lam_plan_s* P) {
   P->off_cy = take((size_t)p.n1 * P->rsize);
   P->off_cx = take((size_t)p.n2 * P->rsize);
   P->off_zbase = take((size_t)p.h * sizeof(int));
-  P->off_zw = take((size_t)p.h * 2 * m * P->rsize);
+  P->off_zdelta = take((size_t)p.h * P->rsize);
   P->off_cth = take((size_t)p.ntheta * sizeof(double));
   P->off_sth = take((size_t)p.ntheta * sizeof(double));
   P->off_rc = take(16 * sizeof(double));
   P->off_line = take(6 * (size_t)p.ntheta * sizeof(double));
-  P->off_zq_ptr = take(((size_t)P->M0 + 1) * sizeof(int));
-  P->off_zq_av = take((size_t)p.h * 2 * m * sizeof(int));
-  P->off_zq_w = take((size_t)p.h * 2 * m * P->rsize);
+  P->off_zrun = take(2 * (size_t)P->M0 * sizeof(unsigned));
   // per-slice target lists of the tiles (built on the device by lam_set_workspace)
   const int TS = std::min(64, std::min(P->M1, P->M2));
   P->ntx = P->M2 / TS;
@@ -244,12 +244,16 @@ int build(lam_plan_s* P) {
   // launch shapes
   LaunchCfg& c = P->cfg;
   col_cfg(D.log2M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds);
-  // the z adjoint stages h samples per column in the same LDS: shrink the tile if h > M0
-  while (c.z_log2TX > 0 && (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize > 131072) {
+  // the z adjoint stages h samples per column in the same LDS, and both z kernels stage the per-row
+  // bases and offsets and the inverse runs after it: shrink the tile until everything fits
+  const size_t z_tables = (size_t)p.h * (sizeof(int) + P->rsize) + 2 * (size_t)P->M0 * sizeof(unsigned);
+  while (c.z_log2TX > 0 && ((size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize > 131072 ||
+                            (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize + z_tables > kLdsMax)) {
     --c.z_log2TX;
     c.z_threads = (int)std::max<long>(64, ((long)P->M0 << c.z_log2TX) / vpt_of(P->csize));
   }
-  c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize;
+  c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize + z_tables;
+  if (c.z_lds > kLdsMax) return fail(LAM_ERR_ARG, "z kernels do not fit the LDS");
   col_cfg(D.log2M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
   row_cfg(D.log2M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
   row_cfg(ilog2(p.w), p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
@@ -275,7 +279,7 @@ Tables<T> tables(const lam_plan_s* P) {
   t.cy = reinterpret_cast<const T*>(w + P->off_cy);
   t.cx = reinterpret_cast<const T*>(w + P->off_cx);
   t.zbase = reinterpret_cast<const int*>(w + P->off_zbase);
-  t.zw = reinterpret_cast<const T*>(w + P->off_zw);
+  t.zdelta = reinterpret_cast<const T*>(w + P->off_zdelta);
   t.cth = reinterpret_cast<const double*>(w + P->off_cth);
   t.sth = reinterpret_cast<const double*>(w + P->off_sth);
   t.rc = reinterpret_cast<const double*>(w + P->off_rc);
@@ -284,9 +288,7 @@ Tables<T> tables(const lam_plan_s* P) {
   t.toff = reinterpret_cast<const int*>(w + P->off_toff);
   t.gperm = reinterpret_cast<const int*>(w + P->off_gperm);
   t.sperm = reinterpret_cast<const int*>(w + P->off_sperm);
-  t.zq_ptr = reinterpret_cast<const int*>(w + P->off_zq_ptr);
-  t.zq_av = reinterpret_cast<const int*>(w + P->off_zq_av);
-  t.zq_w = reinterpret_cast<const T*>(w + P->off_zq_w);
+  t.zrun = reinterpret_cast<const unsigned*>(w + P->off_zrun);
   return t;
 }
 
@@ -701,17 +703,18 @@ int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes) {
   blobs.emplace_back(p->off_cz, f ? pack<float>(p->cz) : pack<double>(p->cz));
   blobs.emplace_back(p->off_cy, f ? pack<float>(p->cy) : pack<double>(p->cy));
   blobs.emplace_back(p->off_cx, f ? pack<float>(p->cx) : pack<double>(p->cx));
-  blobs.emplace_back(p->off_zw, f ? pack<float>(p->zw) : pack<double>(p->zw));
+  blobs.emplace_back(p->off_zdelta, f ? pack<float>(p->zdelta) : pack<double>(p->zdelta));
   blobs.emplace_back(p->off_cth, pack<double>(p->cth));
   blobs.emplace_back(p->off_sth, pack<double>(p->sth));
   blobs.emplace_back(p->off_rc, pack<double>(p->rc));
   blobs.emplace_back(p->off_line, pack<double>(p->line));
-  blobs.emplace_back(p->off_zq_w, f ? pack<float>(p->zq_w) : pack<double>(p->zq_w));
-  for (auto pr : {std::make_pair(p->off_zbase, &p->zbase), std::make_pair(p->off_zq_ptr, &p->zq_ptr),
-                  std::make_pair(p->off_zq_av, &p->zq_av)}) {
-    std::vector<unsigned char> b(pr.second->size() * sizeof(int));
-    std::memcpy(b.data(), pr.second->data(), b.size());
-    blobs.emplace_back(pr.first, std::move(b));
+  {
+    std::vector<unsigned char> b(p->zbase.size() * sizeof(int));
+    std::memcpy(b.data(), p->zbase.data(), b.size());
+    blobs.emplace_back(p->off_zbase, std::move(b));
+    std::vector<unsigned char> r(p->zrun.size() * sizeof(unsigned));
+    std::memcpy(r.data(), p->zrun.data(), r.size());
+    blobs.emplace_back(p->off_zrun, std::move(r));
   }
   for (auto& b : blobs) {
     const hipError_t e = hipMemcpy(w + b.first, b.second.data(), b.second.size(), hipMemcpyHostToDevice);

@@ -176,13 +176,6 @@ template <int MH> constexpr int group_width() { return 2 * MH <= 2 ? 2 : (2 * MH
 // exponential is single precision: relative error below 2e-6 at the stencil
 // edge, 1e-7 at its centre); for complex128 in FP64.  The gather and the
 // spread call the same code, so they stay an exact adjoint pair.
-struct GaussW {
-  double beta;
-  __device__ __forceinline__ float operator()(float a, float) const {
-    return __builtin_amdgcn_exp2f(-(float)(beta * 1.4426950408889634074) * a * a);
-  }
-  __device__ __forceinline__ double operator()(double a, double) const { return exp(-beta * a * a); }
-};
 
 template <typename T, int MH>
 __device__ __forceinline__ void lane_stencil(double sx, double sy, double beta, int j, int& bx, int& by, T* wy,

@@ -22,15 +22,13 @@ struct Tables {
   const T* cz;        // deconvolution factors along z, y, x
   const T* cy;
   const T* cx;
-  const int* zbase;   // [h] floor(R xi_z)
-  const T* zw;        // [h][2m] z-gather weights
+  const int* zbase;   // [h] floor(R xi_z) of detector row k_v
+  const T* zdelta;    // [h] R xi_z - floor(R xi_z)
   const double* cth;  // [ntheta] cos(theta)
   const double* sth;  // [ntheta] sin(theta)
   const double* rc;   // [2m] exp(-beta (2 o + 1)), o = -m+1 ..
   const double* line; // [ntheta][6] per angle: A_x, 1/A_x, C_x, A_y, 1/A_y, C_y (s = A k_u + C k_v/h-units, 1/A = 0 if |A| < 1e-8)
-  const int* zq_ptr;  // [M0 + 1] inverse z table: for grid point q, entries zq_ptr[q] .. zq_ptr[q+1]
-  const int* zq_av;   // [h 2m] k_v index of each entry
-  const T* zq_w;      // [h 2m] weight of each entry
+  const unsigned* zrun; // [M0][2] rows whose z stencil covers grid point q: runs start | count << 16
   const int* tlist;   // per slice [n_theta w]: targets sorted by (tile, border class), t * 4096 + k_u index
   const int* toff;    // per slice [n_tiles 9 + 1]: offsets of the (tile, class) lists within the slice
   const int* gperm;   // per slice [n_tiles]: tiles in decreasing order of gather work

@@ -36,6 +36,13 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   const int tid = threadIdx.x, nth = blockDim.x;
   const size_t plane = (size_t)D.n1 * D.n2;
   const cpx<T> zero = mk((T)0, (T)0);
+  // per-row stencil bases and offsets, after the buffer (its size is shared with the z adjoint)
+  int* zb = reinterpret_cast<int*>(buf + (size_t)max(M0, D.h) * TX);
+  T* zd = reinterpret_cast<T*>(zb + D.h);
+  for (int e = tid; e < D.h; e += nth) {
+    zb[e] = tb.zbase[e];
+    zd[e] = tb.zdelta[e];
+  }
   for (int e = tid; e < (M0 - n0) * TX; e += nth) buf[(n0 / 2) * TX + e] = zero;
   {
     // all global loads of this thread are issued before the first LDS store
@@ -59,27 +66,30 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   }
   __syncthreads();
   lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
+  const GaussW gw{D.beta};
   for (int e = tid; e < D.h * TX; e += nth) {
     const int av = e >> log2TX, b = e & (TX - 1);
-    const int base = tb.zbase[av] - MH + 1;
-    const T* w = tb.zw + av * 2 * MH;
+    const int base = zb[av] - MH + 1;
+    const T dl = zd[av];
     T ax = 0, ay = 0;
 #pragma unroll
     for (int i = 0; i < 2 * MH; ++i) {
+      const T w = gw(dl - (T)(i + 1 - MH), T());
       const cpx<T> g = buf[((base + i) & (M0 - 1)) * TX + b];
-      ax += w[i] * g.x;
-      ay += w[i] * g.y;
+      ax += w * g.x;
+      ay += w * g.y;
     }
     u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b] = mk(ax, ay);
   }
 }
 
 // F*_u1D: the transpose of the z gather, evaluated as a gather through the
-// inverse table (for every grid point q of the oversampled line, the (k_v,
-// weight) pairs whose stencil covers q), so no atomics are needed: stage the
-// h samples of TX columns in LDS, form each grid value in registers, write
-// the grid over the staging area, inverse FFT (conj-FFT-conj), crop,
-// deconvolve.
+// inverse map (for every grid point q of the oversampled line, the run(s) of
+// detector rows whose stencil covers q; the weights are evaluated from the
+// rows' fractional offsets exactly as the forward does), so no atomics are
+// needed: stage the h samples of TX columns in LDS, form each grid value in
+// registers, write the grid over the staging area, inverse FFT
+// (conj-FFT-conj), crop, deconvolve.
 template <typename T, int MH, bool REAL_OUT>
 __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, void* __restrict__ uout, Dims D,
                                                Tables<T> tb, int log2TX, int y0, size_t out_zs) {
@@ -89,6 +99,15 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   const int tid = threadIdx.x, nth = blockDim.x;
   const size_t plane = (size_t)D.n1 * D.n2;
+  // per-row stencil bases and offsets and the inverse runs, after the buffer
+  int* zb = reinterpret_cast<int*>(buf + (size_t)max(M0, D.h) * TX);
+  T* zd = reinterpret_cast<T*>(zb + D.h);
+  unsigned* zr = reinterpret_cast<unsigned*>(zd + D.h);
+  for (int e = tid; e < D.h; e += nth) {
+    zb[e] = tb.zbase[e];
+    zd[e] = tb.zdelta[e];
+  }
+  for (int e = tid; e < 2 * M0; e += nth) zr[e] = tb.zrun[e];
   for (int e0 = 0; e0 < D.h * TX; e0 += vpt<T>() * nth) {
     cpx<T> g[vpt<T>()];
 #pragma unroll
@@ -104,6 +123,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     }
   }
   __syncthreads();
+  const GaussW gw{D.beta};
   cpx<T> v[vpt<T>()];
   const int total = M0 * TX;
 #pragma unroll
@@ -112,12 +132,18 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     T ax = 0, ay = 0;
     if (e < total) {
       const int q = e >> log2TX, b = e & (TX - 1);
-      const int beg = tb.zq_ptr[q], end = tb.zq_ptr[q + 1];
-      for (int j = beg; j < end; ++j) {
-        const T w = tb.zq_w[j];
-        const cpx<T> g = buf[tb.zq_av[j] * TX + b];
-        ax += w * g.x;
-        ay += w * g.y;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const unsigned run = zr[2 * q + r];
+        const int a0 = (int)(run & 0xffffu), a1 = a0 + (int)(run >> 16);
+        for (int av = a0; av < a1; ++av) {
+          // the stencil tap of row av that lands on q
+          const int i = (q - zb[av] + MH - 1) & (M0 - 1);
+          const T w = gw(zd[av] - (T)(i + 1 - MH), T());
+          const cpx<T> g = buf[av * TX + b];
+          ax += w * g.x;
+          ay += w * g.y;
+        }
       }
     }
     v[it] = mk(ax, ay);
