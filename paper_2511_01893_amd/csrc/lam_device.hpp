@@ -86,6 +86,29 @@ template <typename T, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
 // banks; with it, those stores spread over every bank.
 template <bool PAD> __device__ __forceinline__ int lpad(int e) { return PAD ? e + (e >> 3) : e; }
 
+// Multiply v[1..R-1] by the twiddles w^r, w = exp(-2 pi i k / span), then the
+// R-point DFT.  w and w^4 come from the FP64-built table, the other powers by
+// at most two complex products (two table loads per radix-8 butterfly instead
+// of seven).
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_dft(cpx<T>* v, const cpx<T>* __restrict__ tw, int k, int twsh) {
+  cpx<T> tw_r[R];
+  tw_r[1] = tw[k << twsh];
+  if constexpr (R >= 4) {
+    tw_r[2] = cmul(tw_r[1], tw_r[1]);
+    tw_r[3] = cmul(tw_r[2], tw_r[1]);
+  }
+  if constexpr (R == 8) {
+    tw_r[4] = tw[(4 * k) << twsh];
+    tw_r[5] = cmul(tw_r[4], tw_r[1]);
+    tw_r[6] = cmul(tw_r[4], tw_r[2]);
+    tw_r[7] = cmul(tw_r[4], tw_r[3]);
+  }
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw_r[r]);
+  dftR<T, R>(v);
+}
+
 template <typename T, int R, int VPT, bool PAD = false>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, int Ns, int log2span, int sp, int sb,
                                           bool bfast, const cpx<T>* __restrict__ tw, int log2tw, int nth) {
@@ -117,23 +140,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int log2n, int log2nb, in
       if (bfast) { b = t & ((1 << log2nb) - 1); j = t >> log2nb; }
       else { j = t & (nbf - 1); b = t >> log2nbf; }
       const int k = j & (Ns - 1);
-      // the R-1 twiddles w^r, w = exp(-2 pi i k / span): w and w^4 from the FP64-built table, the rest
-      // by at most two complex products (two table loads per radix-8 butterfly instead of seven)
-      cpx<T> tw_r[R];
-      tw_r[1] = tw[k << twsh];
-      if constexpr (R >= 4) {
-        tw_r[2] = cmul(tw_r[1], tw_r[1]);
-        tw_r[3] = cmul(tw_r[2], tw_r[1]);
-      }
-      if constexpr (R == 8) {
-        tw_r[4] = tw[(4 * k) << twsh];
-        tw_r[5] = cmul(tw_r[4], tw_r[1]);
-        tw_r[6] = cmul(tw_r[4], tw_r[2]);
-        tw_r[7] = cmul(tw_r[4], tw_r[3]);
-      }
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw_r[r]);
-      dftR<T, R>(v[it]);
+      twiddle_dft<T, R>(v[it], tw, k, twsh);
       const int idxD = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[lpad<PAD>((idxD + r * Ns) * sp + b * sb)] = v[it][r];
@@ -157,6 +164,60 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int log2n, int log2nb, int 
       fft_stage<T, 2, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw, nth);
       Ns <<= 1; lspan += 1; rem -= 1;
     }
+  }
+}
+
+// The same FFT with the transform length N = 2^LOG2N and the batch NB =
+// 2^LOG2NB fixed at compile time (the hot sizes): every index is a shift or a
+// constant, the stage sequence is unrolled and the work-group size is the
+// launch's, max(64, N NB / VPT).  COLS selects the layout: element (p, b) at
+// p NB + b with the batch index fastest across threads (column blocks), or at
+// b N + p with the butterfly index fastest (row blocks).
+template <typename T, int R, int VPT, bool PAD, int LOG2N, int LOG2NB, bool COLS, int LOG2NS>
+__device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, const cpx<T>* __restrict__ tw, int log2tw) {
+  constexpr int LR = (R == 8) ? 3 : (R == 4 ? 2 : 1);
+  constexpr int LOG2NBF = LOG2N - LR, NBF = 1 << LOG2NBF, NS = 1 << LOG2NS;
+  constexpr int TOTAL = 1 << (LOG2NBF + LOG2NB);                       // butterflies of the stage
+  constexpr int NTH = ((1 << (LOG2N + LOG2NB)) / VPT) < 64 ? 64 : ((1 << (LOG2N + LOG2NB)) / VPT);
+  constexpr int IT = (TOTAL + NTH - 1) / NTH;
+  auto at = [](int p, int b) { return lpad<PAD>(COLS ? (p << LOG2NB) + b : (b << LOG2N) + p); };
+  const int tid = threadIdx.x;
+  cpx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * NTH;
+    if (TOTAL % NTH == 0 || t < TOTAL) {
+      const int j = COLS ? t >> LOG2NB : t & (NBF - 1), b = COLS ? t & ((1 << LOG2NB) - 1) : t >> LOG2NBF;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = buf[at(j + r * NBF, b)];
+    }
+  }
+  __syncthreads();
+  const int twsh = log2tw - (LOG2NS + LR);
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * NTH;
+    if (TOTAL % NTH == 0 || t < TOTAL) {
+      const int j = COLS ? t >> LOG2NB : t & (NBF - 1), b = COLS ? t & ((1 << LOG2NB) - 1) : t >> LOG2NBF;
+      const int k = j & (NS - 1);
+      twiddle_dft<T, R>(v[it], tw, k, twsh);
+      const int idxD = ((j >> LOG2NS) << (LOG2NS + LR)) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[at(idxD + r * NS, b)] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int VPT, bool PAD, int LOG2N, int LOG2NB, bool COLS, int REM = LOG2N, int LOG2NS = 0>
+__device__ __forceinline__ void lds_fft_ct(cpx<T>* buf, const cpx<T>* __restrict__ tw, int log2tw) {
+  if constexpr (REM >= 3) {
+    fft_stage_ct<T, 8, VPT, PAD, LOG2N, LOG2NB, COLS, LOG2NS>(buf, tw, log2tw);
+    lds_fft_ct<T, VPT, PAD, LOG2N, LOG2NB, COLS, REM - 3, LOG2NS + 3>(buf, tw, log2tw);
+  } else if constexpr (REM == 2) {
+    fft_stage_ct<T, 4, VPT, PAD, LOG2N, LOG2NB, COLS, LOG2NS>(buf, tw, log2tw);
+  } else if constexpr (REM == 1) {
+    fft_stage_ct<T, 2, VPT, PAD, LOG2N, LOG2NB, COLS, LOG2NS>(buf, tw, log2tw);
   }
 }
 

@@ -23,17 +23,41 @@ extern __shared__ __align__(16) unsigned char lam_smem[];
 
 __device__ __forceinline__ int sgn_parity(int k) { return (k & 1) ? -1 : 1; }
 
+// The FFT kernels take template sizes LN (log2 of the transform length) and LB (log2 of the
+// transforms per block): LN = 0 selects the general kernel (sizes from the arguments); otherwise the
+// sizes are compile-time constants (the hot sizes) and the compile-time LDS FFT runs.
+template <typename T, int LN, int LB> constexpr int ct_threads() {
+  return ((1 << (LN + LB)) / vpt<T>()) < 64 ? 64 : ((1 << (LN + LB)) / vpt<T>());
+}
+template <typename T, int LN, int LB> __device__ __forceinline__ int block_threads() {
+  if constexpr (LN > 0) return ct_threads<T, LN, LB>();
+  else return (int)blockDim.x;
+}
+// column blocks: element (p, b) at p 2^log2TX + b
+template <typename T, int LN, int LB>
+__device__ __forceinline__ void fft_cols(cpx<T>* buf, int log2N, int log2TX, const Tables<T>& tb, int nth) {
+  if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), false, LN, LB, true>(buf, tb.tw, tb.log2tw);
+  else lds_fft<T, vpt<T>()>(buf, log2N, log2TX, 1 << log2TX, 1, true, tb.tw, tb.log2tw, nth);
+}
+// row blocks: element (p, b) at b 2^log2N + p, one pad slot per 8 elements
+template <typename T, int LN, int LB>
+__device__ __forceinline__ void fft_rows(cpx<T>* buf, int log2N, int log2RB, const Tables<T>& tb, int nth) {
+  if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), true, LN, LB, false>(buf, tb.tw, tb.log2tw);
+  else lds_fft<T, vpt<T>(), true>(buf, log2N, log2RB, 1, 1 << log2N, false, tb.tw, tb.log2tw, nth);
+}
+
 // ---------------------------------------------------------------------------
 // F_u1D
 // ---------------------------------------------------------------------------
-template <typename T, int MH, bool REAL_IN>
+template <typename T, int MH, bool REAL_IN, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx<T>* __restrict__ u1, Dims D,
-                                               Tables<T> tb, int log2TX, int y0, size_t in_zs) {
+                                               Tables<T> tb, int log2TX_, int y0, size_t in_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int TX = 1 << log2TX, M0 = 1 << D.log2M0, n0 = D.n0;
+  const int log2TX = LN > 0 ? LB : log2TX_, log2M0 = LN > 0 ? LN : D.log2M0;
+  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = D.n0;
   // blockIdx.y is the row within the input slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const size_t plane = (size_t)D.n1 * D.n2;
   const cpx<T> zero = mk((T)0, (T)0);
   // per-row stencil bases and offsets, after the buffer (its size is shared with the z adjoint)
@@ -65,7 +89,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
+  fft_cols<T, LN, LB>(buf, log2M0, log2TX, tb, nth);
   const GaussW gw{D.beta};
   for (int e = tid; e < D.h * TX; e += nth) {
     const int av = e >> log2TX, b = e & (TX - 1);
@@ -90,14 +114,15 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
 // needed: stage the h samples of TX columns in LDS, form each grid value in
 // registers, write the grid over the staging area, inverse FFT
 // (conj-FFT-conj), crop, deconvolve.
-template <typename T, int MH, bool REAL_OUT>
+template <typename T, int MH, bool REAL_OUT, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, void* __restrict__ uout, Dims D,
-                                               Tables<T> tb, int log2TX, int y0, size_t out_zs) {
+                                               Tables<T> tb, int log2TX_, int y0, size_t out_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int TX = 1 << log2TX, M0 = 1 << D.log2M0, n0 = D.n0;
+  const int log2TX = LN > 0 ? LB : log2TX_, log2M0 = LN > 0 ? LN : D.log2M0;
+  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = D.n0;
   // blockIdx.y is the row within the output slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const size_t plane = (size_t)D.n1 * D.n2;
   // per-row stencil bases and offsets and the inverse runs, after the buffer
   int* zb = reinterpret_cast<int*>(buf + (size_t)max(M0, D.h) * TX);
@@ -155,7 +180,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     if (e < total) buf[e] = v[it];
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M0, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
+  fft_cols<T, LN, LB>(buf, log2M0, log2TX, tb, nth);
   for (int e = tid; e < n0 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     const cpx<T> g = buf[((a - n0 / 2) & (M0 - 1)) * TX + b];
@@ -169,13 +194,14 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
 // ---------------------------------------------------------------------------
 // F_u2D / F*_u2D equispaced parts
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1, cpx<T>* __restrict__ Tb, int k0,
-                                                   Dims D, Tables<T> tb, int log2TX) {
+                                                   Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int TX = 1 << log2TX, M1 = 1 << D.log2M1, n1 = D.n1, n2 = D.n2;
+  const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
+  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = D.n1, n2 = D.n2;
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
   for (int e = tid; e < (M1 - n1) * TX; e += nth) buf[(n1 / 2) * TX + e] = zero;
   {
@@ -195,20 +221,21 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M1, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
+  fft_cols<T, LN, LB>(buf, log2M1, log2TX, tb, nth);
   for (int e = tid; e < M1 * TX; e += nth) {
     const int q = e >> log2TX, b = e & (TX - 1);
     Tb[((size_t)kk * M1 + q) * n2 + x0 + b] = buf[e];
   }
 }
 
-template <typename T>
+template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb, cpx<T>* __restrict__ u1, int k0,
-                                                   Dims D, Tables<T> tb, int log2TX) {
+                                                   Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int TX = 1 << log2TX, M1 = 1 << D.log2M1, n1 = D.n1, n2 = D.n2;
+  const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
+  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = D.n1, n2 = D.n2;
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> v[vpt<T>()];
 #pragma unroll
@@ -223,7 +250,7 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, D.log2M1, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
+  fft_cols<T, LN, LB>(buf, log2M1, log2TX, tb, nth);
   for (int e = tid; e < n1 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     const cpx<T> v = buf[((a - n1 / 2) & (M1 - 1)) * TX + b];
@@ -232,13 +259,14 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
   }
 }
 
-template <typename T>
+template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb, cpx<T>* __restrict__ Gb, Dims D,
-                                                   Tables<T> tb, int log2RB) {
+                                                   Tables<T> tb, int log2RB_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int RB = 1 << log2RB, M2 = 1 << D.log2M2, n2 = D.n2, log2n2 = D.log2M2 - 1;
+  const int log2RB = LN > 0 ? LB : log2RB_, log2M2 = LN > 0 ? LN : D.log2M2;
+  const int RB = 1 << log2RB, M2 = 1 << log2M2, n2 = M2 / 2, log2n2 = log2M2 - 1;
   const size_t r0 = (size_t)blockIdx.x * RB;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
   // R = 2: the padded positions of each row are [n2/2, M2 - n2/2), n2 of them
   {
@@ -259,17 +287,18 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw, nth);
+  fft_rows<T, LN, LB>(buf, log2M2, log2RB, tb, nth);
   for (int e = tid; e < RB * M2; e += nth) Gb[r0 * M2 + e] = buf[lpad<true>(e)];
 }
 
-template <typename T>
+template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb, cpx<T>* __restrict__ Tb, Dims D,
-                                                   Tables<T> tb, int log2RB) {
+                                                   Tables<T> tb, int log2RB_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int RB = 1 << log2RB, M2 = 1 << D.log2M2, n2 = D.n2, log2n2 = D.log2M2 - 1;
+  const int log2RB = LN > 0 ? LB : log2RB_, log2M2 = LN > 0 ? LN : D.log2M2;
+  const int RB = 1 << log2RB, M2 = 1 << log2M2, n2 = M2 / 2, log2n2 = log2M2 - 1;
   const size_t r0 = (size_t)blockIdx.x * RB;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> v[vpt<T>()];
 #pragma unroll
@@ -284,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>(), true>(buf, D.log2M2, log2RB, 1, M2, false, tb.tw, tb.log2tw, nth);
+  fft_rows<T, LN, LB>(buf, log2M2, log2RB, tb, nth);
   for (int e = tid; e < RB * n2; e += nth) {
     const int b = e >> log2n2, a = e & (n2 - 1);
     Tb[(r0 + b) * n2 + a] = conj(buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))]);
@@ -297,13 +326,14 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
 // before the row pass and after the column pass (h, w multiples of 4).
 // The inverse transform is conj(FFT(conj(.))).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, int log2L,
-                                                 int log2h, int log2RB, int inverse, Tables<T> tb) {
+template <typename T, int LN = 0, int LB = 0>
+__global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, int log2L_,
+                                                 int log2h, int log2RB_, int inverse, Tables<T> tb) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
+  const int log2RB = LN > 0 ? LB : log2RB_, log2L = LN > 0 ? LN : log2L_;
   const int RB = 1 << log2RB, L = 1 << log2L;
   const size_t r0 = (size_t)blockIdx.x * RB;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const int hmask = (1 << log2h) - 1;
   {
     cpx<T> w[vpt<T>()];
@@ -324,21 +354,22 @@ __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, 
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>(), true>(buf, log2L, log2RB, 1, L, false, tb.tw, tb.log2tw, nth);
+  fft_rows<T, LN, LB>(buf, log2L, log2RB, tb, nth);
   for (int e = tid; e < RB * L; e += nth) {
     const cpx<T> v = buf[lpad<true>(e)];
     out[r0 * L + e] = inverse ? conj(v) : v;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, int log2h,
-                                                 int log2w, int log2TX, int inverse, T scale, Tables<T> tb) {
+template <typename T, int LN = 0, int LB = 0>
+__global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, int log2h_,
+                                                 int log2w, int log2TX_, int inverse, T scale, Tables<T> tb) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
+  const int log2TX = LN > 0 ? LB : log2TX_, log2h = LN > 0 ? LN : log2h_;
   const int TX = 1 << log2TX, H = 1 << log2h, W = 1 << log2w;
   const int p0 = blockIdx.x * TX;
   const size_t base = (size_t)blockIdx.y * H * W;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> w[vpt<T>()];
 #pragma unroll
@@ -353,7 +384,7 @@ __global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, 
     }
   }
   __syncthreads();
-  lds_fft<T, vpt<T>()>(buf, log2h, log2TX, TX, 1, true, tb.tw, tb.log2tw, nth);
+  fft_cols<T, LN, LB>(buf, log2h, log2TX, tb, nth);
   for (int e = tid; e < H * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     cpx<T> v = buf[e];
@@ -385,112 +416,157 @@ static hipError_t prep(Kern k, size_t lds) {
     default: { constexpr int MH = 8; __VA_ARGS__; } break; \
   }
 
+// Compile-time-size kernels for the hot (log2 N, log2 batch) pairs, when the configured work-group
+// size matches; the general kernel otherwise.  STMT names LN and LB.
+#define LAM_CT_CASE(T_, L2N, L2B, THR, ln, lb, STMT)                          \
+  else if (L2N == ln && L2B == lb && THR == ct_threads<T_, ln, lb>()) {      \
+    constexpr int LN = ln, LB = lb;                                          \
+    STMT;                                                                    \
+  }
+#define LAM_CT_COLS(T_, L2N, L2B, THR, STMT)                                  \
+  if (false) {}                                                              \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 10, 4, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 10, 3, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 9, 4, STMT)                                 \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 9, 3, STMT)                                 \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 11, 3, STMT)                                \
+  else {                                                                     \
+    constexpr int LN = 0, LB = 0;                                            \
+    STMT;                                                                    \
+  }
+#define LAM_CT_ROWS(T_, L2N, L2B, THR, STMT)                                  \
+  if (false) {}                                                              \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 10, 2, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 10, 1, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 9, 3, STMT)                                 \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 9, 2, STMT)                                 \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 11, 1, STMT)                                \
+  else {                                                                     \
+    constexpr int LN = 0, LB = 0;                                            \
+    STMT;                                                                    \
+  }
+
+template <typename Kern, typename... Args>
+static hipError_t launch(Kern k, dim3 grid, int threads, size_t lds, hipStream_t s, Args... args) {
+  const hipError_t e = prep(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, grid, dim3(threads), lds, s, args...);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, int y0, int ny, size_t in_zs,
                        const Dims& D, const Tables<T>& tb, hipStream_t s) {
-  dim3 grid(D.n2 >> c.z_log2TX, ny);
+  const dim3 grid(D.n2 >> c.z_log2TX, ny);
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
-    if (real_in) {
-      auto k = k_zfwd<T, MH, true>;
-      if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
+    if constexpr (MH == 4) {
+      if (real_in) {
+        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+                    e = launch(k_zfwd<T, MH, true, LN, LB>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX,
+                               y0, in_zs))
+      } else {
+        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+                    e = launch(k_zfwd<T, MH, false, LN, LB>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX,
+                               y0, in_zs))
+      }
     } else {
-      auto k = k_zfwd<T, MH, false>;
-      if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
+      e = real_in ? launch(k_zfwd<T, MH, true>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs)
+                  : launch(k_zfwd<T, MH, false>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
     }
   });
-  return hipGetLastError();
+  return e;
 }
 
 template <typename T>
 hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, int y0, int ny, size_t out_zs,
                        const Dims& D, const Tables<T>& tb, hipStream_t s) {
-  dim3 grid(D.n2 >> c.z_log2TX, ny);
+  const dim3 grid(D.n2 >> c.z_log2TX, ny);
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
-    if (real_out) {
-      auto k = k_zadj<T, MH, true>;
-      if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
+    if constexpr (MH == 4) {
+      if (real_out) {
+        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+                    e = launch(k_zadj<T, MH, true, LN, LB>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX,
+                               y0, out_zs))
+      } else {
+        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+                    e = launch(k_zadj<T, MH, false, LN, LB>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX,
+                               y0, out_zs))
+      }
     } else {
-      auto k = k_zadj<T, MH, false>;
-      if ((e = prep(k, c.z_lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, dim3(c.z_threads), c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
+      e = real_out ? launch(k_zadj<T, MH, true>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs)
+                   : launch(k_zadj<T, MH, false>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
     }
   });
-  return hipGetLastError();
+  return e;
 }
 
 template <typename T>
 hipError_t launch_ycol_fwd(const LaunchCfg& c, const cpx<T>* u1, cpx<T>* Tb, int k0, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s) {
-  auto k = k_ycol_fwd<T>;
-  hipError_t e = prep(k, c.y_lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(D.n2 >> c.y_log2TX, ns), dim3(c.y_threads), c.y_lds, s, u1, Tb, k0, D, tb, c.y_log2TX);
-  return hipGetLastError();
+  const dim3 grid(D.n2 >> c.y_log2TX, ns);
+  hipError_t e = hipSuccess;
+  LAM_CT_COLS(T, D.log2M1, c.y_log2TX, c.y_threads,
+              e = launch(k_ycol_fwd<T, LN, LB>, grid, c.y_threads, c.y_lds, s, u1, Tb, k0, D, tb, c.y_log2TX))
+  return e;
 }
 
 template <typename T>
 hipError_t launch_xrow_fwd(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* Gb, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s) {
-  auto k = k_xrow_fwd<T>;
-  hipError_t e = prep(k, c.x_lds);
-  if (e != hipSuccess) return e;
-  const size_t rows = (size_t)ns << D.log2M1;
-  hipLaunchKernelGGL(k, dim3((unsigned)(rows >> c.x_log2RB)), dim3(c.x_threads), c.x_lds, s, Tb, Gb, D, tb,
-                     c.x_log2RB);
-  return hipGetLastError();
+  const dim3 grid((unsigned)(((size_t)ns << D.log2M1) >> c.x_log2RB));
+  hipError_t e = hipSuccess;
+  LAM_CT_ROWS(T, D.log2M2, c.x_log2RB, c.x_threads,
+              e = launch(k_xrow_fwd<T, LN, LB>, grid, c.x_threads, c.x_lds, s, Tb, Gb, D, tb, c.x_log2RB))
+  return e;
 }
 
 template <typename T>
 hipError_t launch_xrow_adj(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* Tb, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s) {
-  auto k = k_xrow_adj<T>;
-  hipError_t e = prep(k, c.x_lds);
-  if (e != hipSuccess) return e;
-  const size_t rows = (size_t)ns << D.log2M1;
-  hipLaunchKernelGGL(k, dim3((unsigned)(rows >> c.x_log2RB)), dim3(c.x_threads), c.x_lds, s, Gb, Tb, D, tb,
-                     c.x_log2RB);
-  return hipGetLastError();
+  const dim3 grid((unsigned)(((size_t)ns << D.log2M1) >> c.x_log2RB));
+  hipError_t e = hipSuccess;
+  LAM_CT_ROWS(T, D.log2M2, c.x_log2RB, c.x_threads,
+              e = launch(k_xrow_adj<T, LN, LB>, grid, c.x_threads, c.x_lds, s, Gb, Tb, D, tb, c.x_log2RB))
+  return e;
 }
 
 template <typename T>
 hipError_t launch_ycol_adj(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* u1, int k0, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s) {
-  auto k = k_ycol_adj<T>;
-  hipError_t e = prep(k, c.y_lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(D.n2 >> c.y_log2TX, ns), dim3(c.y_threads), c.y_lds, s, Tb, u1, k0, D, tb, c.y_log2TX);
-  return hipGetLastError();
+  const dim3 grid(D.n2 >> c.y_log2TX, ns);
+  hipError_t e = hipSuccess;
+  LAM_CT_COLS(T, D.log2M1, c.y_log2TX, c.y_threads,
+              e = launch(k_ycol_adj<T, LN, LB>, grid, c.y_threads, c.y_lds, s, Tb, u1, k0, D, tb, c.y_log2TX))
+  return e;
 }
 
 template <typename T>
 hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, int nproj, const Dims& D,
                          const Tables<T>& tb, hipStream_t s) {
   const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
-  auto k = k_rowfft<T>;
-  hipError_t e = prep(k, c.r_lds);
-  if (e != hipSuccess) return e;
-  const size_t rows = (size_t)nproj * D.h;
-  hipLaunchKernelGGL(k, dim3((unsigned)(rows >> c.r_log2RB)), dim3(c.r_threads), c.r_lds, s, in, out, log2w, log2h,
-                     c.r_log2RB, inverse ? 1 : 0, tb);
-  return hipGetLastError();
+  const dim3 grid((unsigned)(((size_t)nproj * D.h) >> c.r_log2RB));
+  const int inv = inverse ? 1 : 0;
+  hipError_t e = hipSuccess;
+  LAM_CT_ROWS(T, log2w, c.r_log2RB, c.r_threads,
+              e = launch(k_rowfft<T, LN, LB>, grid, c.r_threads, c.r_lds, s, in, out, log2w, log2h, c.r_log2RB, inv,
+                         tb))
+  return e;
 }
 
 template <typename T>
 hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale_d, int nproj,
                          const Dims& D, const Tables<T>& tb, hipStream_t s) {
   const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
-  auto k = k_colfft<T>;
-  hipError_t e = prep(k, c.c_lds);
-  if (e != hipSuccess) return e;
+  const dim3 grid(D.w >> c.c_log2TX, nproj);
   const T scale = (T)scale_d;
-  hipLaunchKernelGGL(k, dim3(D.w >> c.c_log2TX, nproj), dim3(c.c_threads), c.c_lds, s, in, out, log2h, log2w,
-                     c.c_log2TX, inverse ? 1 : 0, scale, tb);
-  return hipGetLastError();
+  const int inv = inverse ? 1 : 0;
+  hipError_t e = hipSuccess;
+  LAM_CT_COLS(T, log2h, c.c_log2TX, c.c_threads,
+              e = launch(k_colfft<T, LN, LB>, grid, c.c_threads, c.c_lds, s, in, out, log2h, log2w, c.c_log2TX, inv,
+                         scale, tb))
+  return e;
 }
 
 #define LAM_INST(T)                                                                                              \
