@@ -170,39 +170,72 @@ __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log
 // ---------------------------------------------------------------------------
 template <int MH> constexpr int group_width() { return 2 * MH <= 2 ? 2 : (2 * MH <= 4 ? 4 : (2 * MH <= 8 ? 8 : 16)); }
 
-// The weights exp(-beta (delta - o)^2), o = -m+1 .. m, are evaluated directly:
-// for complex64 as a single-precision 2^x of -beta log2(e) (delta - o)^2 (the
-// fractional offset delta comes from the FP64 coordinate, so only the
-// exponential is single precision: relative error below 2e-6 at the stencil
-// edge, 1e-7 at its centre); for complex128 in FP64.  The gather and the
-// spread call the same code, so they stay an exact adjoint pair.
+// The weights exp(-beta (delta - o)^2), o = -m+1 .. m, of one axis come from
+// three exponentials (fast Gaussian gridding, Greengard & Lee): the centre tap
+// o = 0 (a = delta in [0, 1)) and the ratios to its two neighbours,
+// exp(beta (2 delta - 1)) towards o = 1 and exp(-beta (2 delta + 1)) towards
+// o = -1; each further ratio is the previous one times exp(-2 beta).  The
+// fractional offset delta comes from the FP64 coordinate.  For complex64 the
+// exponentials are single-precision 2^x; the gather runs the recurrence in
+// FP32 (relative weight error below 5e-7), the spread in FP64 on its products
+// with the sample (it accumulates in FP64 anyway).  For complex128 everything
+// is FP64.
+template <typename T>
+struct Fgg;
+template <>
+struct Fgg<float> {
+  float b;    // beta log2(e)
+  double q;   // exp(-2 beta)
+  __device__ explicit Fgg(double beta) : b((float)(beta * 1.4426950408889634074)), q(exp(-2.0 * beta)) {}
+  __device__ __forceinline__ void seeds(float d, float& wc, float& up, float& dn) const {
+    wc = __builtin_amdgcn_exp2f(-b * d * d);
+    up = __builtin_amdgcn_exp2f(b * (2.f * d - 1.f));
+    dn = __builtin_amdgcn_exp2f(-b * (2.f * d + 1.f));
+  }
+  // one weight exp(-beta a^2), evaluated directly
+  __device__ __forceinline__ float one(float a) const { return __builtin_amdgcn_exp2f(-b * a * a); }
+};
+template <>
+struct Fgg<double> {
+  double beta, q;
+  __device__ explicit Fgg(double beta_) : beta(beta_), q(exp(-2.0 * beta_)) {}
+  __device__ __forceinline__ void seeds(double d, double& wc, double& up, double& dn) const {
+    wc = exp(-beta * d * d);
+    up = exp(beta * (2.0 * d - 1.0));
+    dn = exp(-beta * (2.0 * d + 1.0));
+  }
+  __device__ __forceinline__ double one(double a) const { return exp(-beta * a * a); }
+};
 
+// All 2m weights of one axis; w[i] belongs to grid point floor(s) - m + 1 + i.
 template <typename T, int MH>
-__device__ __forceinline__ void lane_stencil(double sx, double sy, double beta, int j, int& bx, int& by, T* wy,
-                                             T& wxj) {
-  const GaussW gw{beta};
-  const double fy = floor(sy), fx = floor(sx);
-  by = (int)fy;
-  bx = (int)fx;
-  const T dy = (T)(sy - fy), dx = (T)(sx - fx);
+__device__ __forceinline__ void fgg_taps(const Fgg<T>& g, T d, T* w) {
+  T wc, up, dn;
+  g.seeds(d, wc, up, dn);
+  const T q = (T)g.q;
+  w[MH - 1] = wc;
+  T x = wc;
 #pragma unroll
-  for (int i = 0; i < 2 * MH; ++i) wy[i] = gw(dy - (T)(i + 1 - MH), T());
-  wxj = j < 2 * MH ? gw(dx - (T)(j + 1 - MH), T()) : (T)0;
+  for (int i = MH; i < 2 * MH; ++i) {
+    x *= up;
+    w[i] = x;
+    up *= q;
+  }
+  x = wc;
+#pragma unroll
+  for (int i = MH - 2; i >= 0; --i) {
+    x *= dn;
+    w[i] = x;
+    dn *= q;
+  }
 }
 
-// All 2m weights along both axes (the gather's one-lane-per-target form).
-template <typename T, int MH>
-__device__ __forceinline__ void full_stencil(double sx, double sy, double beta, int& bx, int& by, T* wx, T* wy) {
-  const GaussW gw{beta};
-  const double fy = floor(sy), fx = floor(sx);
-  by = (int)fy;
-  bx = (int)fx;
-  const T dy = (T)(sy - fy), dx = (T)(sx - fx);
-#pragma unroll
-  for (int i = 0; i < 2 * MH; ++i) {
-    wy[i] = gw(dy - (T)(i + 1 - MH), T());
-    wx[i] = gw(dx - (T)(i + 1 - MH), T());
-  }
+// Position v relative to a tile origin, folded by the grid period M into
+// [-16, M - 16): with TS + 16 <= M and at most 16 taps, a stencil point lies in
+// the tile exactly when its folded position is in [0, TS).
+__device__ __forceinline__ int fold_rel(int v, int M) {
+  const int r = v & (M - 1);
+  return r >= M - 16 ? r - M : r;
 }
 
 // ---------------------------------------------------------------------------
@@ -223,6 +256,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
   const int tx = tix % ntx, ty = tix / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
   const cpx<T>* G = Gb + (size_t)kk * M1 * M2;
+  const Fgg<T> fg(D.beta);
   // e / P by multiplication: exact for e < 2^16 with P < 2^8
   const unsigned magicP = 0xffffffffu / (unsigned)P + 1u;
   for (int e0 = 0; e0 < P * P; e0 += vpt<T>() * nth) {
@@ -267,9 +301,11 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
     for (int u = 0; u < UG; ++u) {
       double sx, sy;
       target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
+      const double fy = floor(sy), fx = floor(sx);
+      const int by = (int)fy, bx = (int)fx;
       T wx[W], wy[W];
-      int bx, by;
-      full_stencil<T, MH>(sx, sy, D.beta, bx, by, wx, wy);
+      fgg_taps<T, MH>(fg, (T)(sx - fx), wx);
+      fgg_taps<T, MH>(fg, (T)(sy - fy), wy);
       const int ox = (bx - x0) & (M2 - 1), oy = (by - y0) & (M1 - 1);
       T ax = 0, ay = 0;
 #pragma unroll
@@ -295,11 +331,17 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
 // column's 2m taps, one stencil row per FP64 LDS atomic (native ds_add_f64;
 // gfx950 runs FP64 LDS atomics ~20x faster than FP32 ones); a wave's 64 adds
 // cover NG targets' rows, GW adjacent cells each.
+//
+// LTS > 0 fixes the tile size 2^LTS at compile time and requires M1, M2 >= 2^LTS + 16: stencil
+// rows and columns are then folded positions relative to the tile, so a row's cell is the row
+// base plus a constant (immediate LDS offsets) and the test for the tile is one compare.
 // ---------------------------------------------------------------------------
-template <typename T, int MH>
+template <typename T, int MH, int LTS = 0>
 __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ Gb, int k0,
-                                                 Dims D, Tables<T> tb, int log2TS) {
+                                                 Dims D, Tables<T> tb, int log2TS_) {
   constexpr int W = 2 * MH, GW = group_width<MH>(), NG = 64 / GW;
+  static_assert(LTS == 0 || W <= 16, "folded positions assume at most 16 taps");
+  const int log2TS = LTS > 0 ? LTS : log2TS_;
   const int TS = 1 << log2TS, PA = TS + 8;   // PA = 8 (mod 32): stencil rows of a target fall in distinct banks
   const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
   const int ntx = M2 >> log2TS, nty = M1 >> log2TS;
@@ -330,6 +372,8 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   constexpr int U = 4;
   const size_t hw = (size_t)D.h * D.w;
   const int kw = k * D.w;
+  const Fgg<T> fg(D.beta);
+  const double qd = fg.q;
   auto spread = [&](int n, auto idx_of) {
     const int stretch = (n + NG * U - 1) / (NG * U);
     for (int i0 = wave; i0 < stretch; i0 += nwave) {
@@ -355,23 +399,55 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
       for (int u = 0; u < U; ++u) {
         double sx, sy;
         target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
-        T wy[W], wxj;
-        int bx, by;
-        lane_stencil<T, MH>(sx, sy, D.beta, j, bx, by, wy, wxj);
-        const int col = (bx - MH + 1 + j - x0) & (M2 - 1);
-        if (ok[u] && j < W && col < TS) {
-          // FP64 products of the FP32 weights and samples: one conversion per weight, not per add
-          const double vx = (double)(wxj * v[u].x), vy = (double)(wxj * v[u].y);
-          const int r0 = by - MH + 1 - y0;
-#pragma unroll
-          for (int iy = 0; iy < W; ++iy) {
-            const int row = (r0 + iy) & (M1 - 1);
-            if (row < TS) {
-              const int a = __umul24(row, PA) + col;
-              const double w = (double)wy[iy];
-              atomicAdd(are + a, w * vx);
-              atomicAdd(aim + a, w * vy);
+        const double fy = floor(sy), fx = floor(sx);
+        const int by = (int)fy, bx = (int)fx;
+        int col, r0;
+        if constexpr (LTS > 0) {
+          col = fold_rel(bx - MH + 1 - x0, M2) + j;
+          r0 = fold_rel(by - MH + 1 - y0, M1);
+        } else {
+          col = (bx - MH + 1 + j - x0) & (M2 - 1);
+          r0 = by - MH + 1 - y0;
+        }
+        if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
+          const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
+          T wc, up, dn;
+          fg.seeds((T)(sy - fy), wc, up, dn);
+          const int ab = r0 * PA + col;   // cell (r0, col); row iy adds iy * PA (folded path)
+          auto add = [&](int iy, double x, double y) {
+            int a;
+            if constexpr (LTS > 0) {
+              if ((unsigned)(r0 + iy) >= (unsigned)TS) return;
+              a = ab + iy * PA;
+            } else {
+              const int row = (r0 + iy) & (M1 - 1);
+              if (row >= TS) return;
+              a = __umul24(row, PA) + col;
             }
+            atomicAdd(are + a, x);
+            atomicAdd(aim + a, y);
+          };
+          // the column's products with the row weights, by the weight recurrence in FP64 from the
+          // centre row outwards
+          const double cx = (double)(wxj * v[u].x) * (double)wc, cy = (double)(wxj * v[u].y) * (double)wc;
+          add(MH - 1, cx, cy);
+          double px = cx, py = cy, r = (double)up;
+#pragma unroll
+          for (int iy = MH; iy < W; ++iy) {
+            px *= r;
+            py *= r;
+            add(iy, px, py);
+            r *= qd;
+          }
+          px = cx;
+          py = cy;
+          r = (double)dn;
+#pragma unroll
+          for (int iy = MH - 2; iy >= 0; --iy) {
+            px *= r;
+            py *= r;
+            add(iy, px, py);
+            r *= qd;
           }
         }
       }
@@ -400,6 +476,9 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
 // host launchers
 // ---------------------------------------------------------------------------
 namespace {
+// 64 x 64 tiles on a grid of at least 128 x 128: the compile-time tile kernels apply
+bool fast_tiles(const LaunchCfg& c, const Dims& D) { return c.g_log2TS == 6 && D.log2M1 >= 7 && D.log2M2 >= 7; }
+
 template <typename Kern>
 hipError_t prep(Kern k, size_t lds) {
   if (lds > 64 * 1024)
@@ -460,7 +539,7 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
                           const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
-    auto k = k_scatter<T, MH>;
+    auto k = MH == 4 && fast_tiles(c, D) ? k_scatter<T, MH, 6> : k_scatter<T, MH>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
     const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
     hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
