@@ -186,7 +186,10 @@ template <>
 struct Fgg<float> {
   float b;    // beta log2(e)
   double q;   // exp(-2 beta)
-  __device__ explicit Fgg(double beta) : b((float)(beta * 1.4426950408889634074)), q(exp(-2.0 * beta)) {}
+  float e2m, e4m, e4p;   // exp(-2 beta), exp(-4 beta), exp(4 beta)
+  __device__ explicit Fgg(double beta)
+      : b((float)(beta * 1.4426950408889634074)), q(exp(-2.0 * beta)), e2m((float)exp(-2.0 * beta)),
+        e4m((float)exp(-4.0 * beta)), e4p((float)exp(4.0 * beta)) {}
   __device__ __forceinline__ void seeds(float d, float& wc, float& up, float& dn) const {
     wc = __builtin_amdgcn_exp2f(-b * d * d);
     up = __builtin_amdgcn_exp2f(b * (2.f * d - 1.f));
@@ -194,18 +197,41 @@ struct Fgg<float> {
   }
   // one weight exp(-beta a^2), evaluated directly
   __device__ __forceinline__ float one(float a) const { return __builtin_amdgcn_exp2f(-b * a * a); }
+  // exp(-beta d^2), exp(-beta (2d + 1)), exp(4 beta (d - 1))
+  __device__ __forceinline__ void three(float d, float& w, float& dn, float& up2) const {
+    w = __builtin_amdgcn_exp2f(-b * d * d);
+    dn = __builtin_amdgcn_exp2f(-b * (2.f * d + 1.f));
+    up2 = __builtin_amdgcn_exp2f(4.f * b * (d - 1.f));
+  }
 };
 template <>
 struct Fgg<double> {
   double beta, q;
-  __device__ explicit Fgg(double beta_) : beta(beta_), q(exp(-2.0 * beta_)) {}
+  double e2m, e4m, e4p;
+  __device__ explicit Fgg(double beta_)
+      : beta(beta_), q(exp(-2.0 * beta_)), e2m(exp(-2.0 * beta_)), e4m(exp(-4.0 * beta_)), e4p(exp(4.0 * beta_)) {}
   __device__ __forceinline__ void seeds(double d, double& wc, double& up, double& dn) const {
     wc = exp(-beta * d * d);
     up = exp(beta * (2.0 * d - 1.0));
     dn = exp(-beta * (2.0 * d + 1.0));
   }
   __device__ __forceinline__ double one(double a) const { return exp(-beta * a * a); }
+  __device__ __forceinline__ void three(double d, double& w, double& dn, double& up2) const {
+    w = exp(-beta * d * d);
+    dn = exp(-beta * (2.0 * d + 1.0));
+    up2 = exp(4.0 * beta * (d - 1.0));
+  }
 };
+
+// Value of the lane 8 places away within the lane's row of 16 (the other half of the row):
+// DPP row rotate by 8, no LDS traffic.
+__device__ __forceinline__ int swap8(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false); }
+__device__ __forceinline__ float swap8(float v) { return __int_as_float(swap8(__float_as_int(v))); }
+__device__ __forceinline__ double swap8(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = swap8((int)(b & 0xffffffff)), hi = swap8((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // All 2m weights of one axis; w[i] belongs to grid point floor(s) - m + 1 + i.
 template <typename T, int MH>
@@ -335,12 +361,21 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
 // LTS > 0 fixes the tile size 2^LTS at compile time and requires M1, M2 >= 2^LTS + 16: stencil
 // rows and columns are then folded positions relative to the tile, so a row's cell is the row
 // base plus a constant (immediate LDS offsets) and the test for the tile is one compare.
+//
+// PAIRS (m = 4 on the folded path) changes only how the adds are laid out.  An atomic
+// instruction whose 8-lane groups each add one row of a different target hits the banks at
+// random (~16 cycles per 64-lane FP64 add); one whose 16-lane rows each add two adjacent
+// rows of one target covers every bank equally (PA = 8 (mod 32) doubles puts the second row
+// 16 banks on) and runs at the minimum (~9 cycles).  So the two 8-lane groups of a 16-lane
+// row evaluate their own targets as before, trade what the other needs through DPP, and then
+// add both targets in turn: lane (h, j) adds column j of the rows of parity h.
 // ---------------------------------------------------------------------------
-template <typename T, int MH, int LTS = 0>
+template <typename T, int MH, int LTS = 0, bool PAIRS = false>
 __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ Gb, int k0,
                                                  Dims D, Tables<T> tb, int log2TS_) {
   constexpr int W = 2 * MH, GW = group_width<MH>(), NG = 64 / GW;
   static_assert(LTS == 0 || W <= 16, "folded positions assume at most 16 taps");
+  static_assert(!PAIRS || (MH == 4 && LTS > 0), "row pairs: m = 4 on the folded path");
   const int log2TS = LTS > 0 ? LTS : log2TS_;
   const int TS = 1 << log2TS, PA = TS + 8;   // PA = 8 (mod 32): stencil rows of a target fall in distinct banks
   const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
@@ -409,7 +444,48 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
           col = (bx - MH + 1 + j - x0) & (M2 - 1);
           r0 = by - MH + 1 - y0;
         }
-        if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
+        if constexpr (PAIRS) {
+          // this lane's target (valid or not, every lane takes part in the DPP exchange)
+          const int h = (lane >> 3) & 1;
+          const bool valid = ok[u] && (unsigned)col < (unsigned)TS;
+          const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
+          const T pvx = wxj * v[u].x, pvy = wxj * v[u].y;
+          // row weights by parity, from d = delta_y: odd rows start at the centre row m - 1
+          // (offset d), even rows at row m - 2 (offset d + 1); two-row ratios up and down
+          T w1, dn1, up1;
+          fg.three((T)(sy - fy), w1, dn1, up1);
+          const T dn1r = dn1 * dn1 * (T)fg.e2m;   // exp(-4 beta (d + 1))
+          const T w0 = w1 * dn1, up0 = up1 * (T)fg.e4p, dn0r = dn1r * (T)fg.e4m;
+          // keep parity h, send parity 1 - h with the column, row base and products
+          const T ws_own = h ? w1 : w0, up_own = h ? up1 : up0, dn_own = h ? dn1r : dn0r;
+          const int col_o = valid ? col : TS;
+          const int colp = swap8(col_o), r0p = swap8(r0);
+          const T pxp = swap8(pvx), pyp = swap8(pvy);
+          const T wsp = swap8(h ? w0 : w1), upp = swap8(h ? up0 : up1), dnp = swap8(h ? dn0r : dn1r);
+          // target of the row's first half, then of its second half
+#pragma unroll
+          for (int ph = 0; ph < 2; ++ph) {
+            const bool own = (h == ph);
+            const int cc = own ? col_o : colp, rs = (own ? r0 : r0p) + MH - 2 + h;
+            const T ax = own ? pvx : pxp, ay = own ? pvy : pyp;
+            const T ws = own ? ws_own : wsp, up = own ? up_own : upp, dn = own ? dn_own : dnp;
+            if ((unsigned)cc < (unsigned)TS) {
+              const int as = rs * PA + cc;
+              auto add = [&](int k2, double x, double y) {   // row rs + k2 (same parity)
+                if ((unsigned)(rs + k2) >= (unsigned)TS) return;
+                atomicAdd(are + as + k2 * PA, x);
+                atomicAdd(aim + as + k2 * PA, y);
+              };
+              const double cx = (double)ax * (double)ws, cy = (double)ay * (double)ws;
+              add(0, cx, cy);
+              const double ru = (double)up, px = cx * ru, py = cy * ru;
+              add(2, px, py);
+              const double ru2 = ru * (double)fg.e4m * (double)fg.e4m;   // next two-row ratio up
+              add(4, px * ru2, py * ru2);
+              add(-2, cx * (double)dn, cy * (double)dn);
+            }
+          }
+        } else if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
           const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
           T wc, up, dn;
           fg.seeds((T)(sy - fy), wc, up, dn);
@@ -539,7 +615,7 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
                           const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
-    auto k = MH == 4 && fast_tiles(c, D) ? k_scatter<T, MH, 6> : k_scatter<T, MH>;
+    auto k = MH == 4 && fast_tiles(c, D) ? k_scatter<T, MH, 6, MH == 4> : k_scatter<T, MH>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
     const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
     hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
