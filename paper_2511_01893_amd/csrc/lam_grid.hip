@@ -16,6 +16,8 @@
 //              border classes of the 8 neighbouring tiles whose stencils
 //              reach in, one lane per stencil column, one FP64 LDS atomic per
 //              stencil row.  Every cell of the tile is then written once.
+#include <type_traits>
+
 #include "lam_internal.hpp"
 
 namespace lam {
@@ -223,13 +225,22 @@ struct Fgg<double> {
   }
 };
 
-// Value of the lane 8 places away within the lane's row of 16 (the other half of the row):
-// DPP row rotate by 8, no LDS traffic.
-__device__ __forceinline__ int swap8(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false); }
-__device__ __forceinline__ float swap8(float v) { return __int_as_float(swap8(__float_as_int(v))); }
-__device__ __forceinline__ double swap8(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = swap8((int)(b & 0xffffffff)), hi = swap8((int)(b >> 32));
+// Half-row exchange through DPP (row rotate by 8 within each row of 16 lanes, no LDS traffic):
+// from_half<H>(own, send) gives lanes of half H their own value and lanes of the other half the
+// value `send` of the lane 8 places away (bank mask: only the other half's two banks are written).
+template <int H>
+__device__ __forceinline__ int from_half(int own, int send) {
+  return __builtin_amdgcn_update_dpp(own, send, 0x128, 0xf, H == 0 ? 0xc : 0x3, false);
+}
+template <int H>
+__device__ __forceinline__ float from_half(float own, float send) {
+  return __int_as_float(from_half<H>(__float_as_int(own), __float_as_int(send)));
+}
+template <int H>
+__device__ __forceinline__ double from_half(double own, double send) {
+  const long long o = __double_as_longlong(own), s = __double_as_longlong(send);
+  const int lo = from_half<H>((int)(o & 0xffffffff), (int)(s & 0xffffffff));
+  const int hi = from_half<H>((int)(o >> 32), (int)(s >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -405,7 +416,7 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   // runs of neighbouring targets, whose stencils overlap, and adds to one cell within an
   // instruction serialise); the U targets of a lane group are independent load chains.
   constexpr int U = 4;
-  const size_t hw = (size_t)D.h * D.w;
+  const unsigned hw = (unsigned)D.h * D.w;   // < 2^24: a 32 x 32 -> 64-bit product per sample
   const int kw = k * D.w;
   const Fgg<T> fg(D.beta);
   const double qd = fg.q;
@@ -421,14 +432,14 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
         const int i = (u * NG + g) * stretch + i0;
         ok[u] = i < n;
         const int pe = ok[u] ? L[idx_of(i)] : 0;
-        t[u] = pe >> 12;
+        t[u] = (int)((unsigned)pe >> 12);
         uk[u] = pe & 4095;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         c[u] = tb.cth[t[u]];
         sn[u] = tb.sth[t[u]];
-        v[u] = in[(size_t)t[u] * hw + kw + uk[u]];
+        v[u] = in[(size_t)(unsigned)t[u] * hw + (unsigned)(kw + uk[u])];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -456,19 +467,16 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
           fg.three((T)(sy - fy), w1, dn1, up1);
           const T dn1r = dn1 * dn1 * (T)fg.e2m;   // exp(-4 beta (d + 1))
           const T w0 = w1 * dn1, up0 = up1 * (T)fg.e4p, dn0r = dn1r * (T)fg.e4m;
-          // keep parity h, send parity 1 - h with the column, row base and products
-          const T ws_own = h ? w1 : w0, up_own = h ? up1 : up0, dn_own = h ? dn1r : dn0r;
+          // this lane keeps its own target's parity-h weights; the other half needs parity 1 - h
+          const T ws_h = h ? w1 : w0, up_h = h ? up1 : up0, dn_h = h ? dn1r : dn0r;
+          const T ws_x = h ? w0 : w1, up_x = h ? up0 : up1, dn_x = h ? dn0r : dn1r;
           const int col_o = valid ? col : TS;
-          const int colp = swap8(col_o), r0p = swap8(r0);
-          const T pxp = swap8(pvx), pyp = swap8(pvy);
-          const T wsp = swap8(h ? w0 : w1), upp = swap8(h ? up0 : up1), dnp = swap8(h ? dn0r : dn1r);
           // target of the row's first half, then of its second half
-#pragma unroll
-          for (int ph = 0; ph < 2; ++ph) {
-            const bool own = (h == ph);
-            const int cc = own ? col_o : colp, rs = (own ? r0 : r0p) + MH - 2 + h;
-            const T ax = own ? pvx : pxp, ay = own ? pvy : pyp;
-            const T ws = own ? ws_own : wsp, up = own ? up_own : upp, dn = own ? dn_own : dnp;
+          auto phase = [&](auto H) {
+            constexpr int ph = decltype(H)::value;
+            const int cc = from_half<ph>(col_o, col_o), rs = from_half<ph>(r0, r0) + MH - 2 + h;
+            const T ax = from_half<ph>(pvx, pvx), ay = from_half<ph>(pvy, pvy);
+            const T ws = from_half<ph>(ws_h, ws_x), up = from_half<ph>(up_h, up_x), dn = from_half<ph>(dn_h, dn_x);
             if ((unsigned)cc < (unsigned)TS) {
               const int as = rs * PA + cc;
               auto add = [&](int k2, double x, double y) {   // row rs + k2 (same parity)
@@ -484,7 +492,9 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
               add(4, px * ru2, py * ru2);
               add(-2, cx * (double)dn, cy * (double)dn);
             }
-          }
+          };
+          phase(std::integral_constant<int, 0>());
+          phase(std::integral_constant<int, 1>());
         } else if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
           const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
           T wc, up, dn;
