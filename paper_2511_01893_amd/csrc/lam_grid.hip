@@ -225,6 +225,20 @@ struct Fgg<double> {
   }
 };
 
+// Value of lane U of the lane's quad (DPP quad_perm broadcast).
+template <int U>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, U * 0x55, 0xf, 0xf, false);
+}
+template <int U>
+__device__ __forceinline__ float quad_bcast(float v) { return __int_as_float(quad_bcast<U>(__float_as_int(v))); }
+template <int U>
+__device__ __forceinline__ double quad_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = quad_bcast<U>((int)(b & 0xffffffff)), hi = quad_bcast<U>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Half-row exchange through DPP (row rotate by 8 within each row of 16 lanes, no LDS traffic):
 // from_half<H>(own, send) gives lanes of half H their own value and lanes of the other half the
 // value `send` of the lane 8 places away (bank mask: only the other half's two banks are written).
@@ -423,48 +437,36 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   auto spread = [&](int n, auto idx_of) {
     const int stretch = (n + NG * U - 1) / (NG * U);
     for (int i0 = wave; i0 < stretch; i0 += nwave) {
-      int t[U], uk[U];
-      bool ok[U];
-      double c[U], sn[U];
-      cpx<T> v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = (u * NG + g) * stretch + i0;
-        ok[u] = i < n;
-        const int pe = ok[u] ? L[idx_of(i)] : 0;
-        t[u] = (int)((unsigned)pe >> 12);
-        uk[u] = pe & 4095;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        c[u] = tb.cth[t[u]];
-        sn[u] = tb.sth[t[u]];
-        v[u] = in[(size_t)(unsigned)t[u] * hw + (unsigned)(kw + uk[u])];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
+      if constexpr (PAIRS) {
+        // Lane (g, j) evaluates target j & 3 of its group's four (coordinates, bases, offsets,
+        // sample); each quad then broadcasts them, so every lane of the group has all four.
+        static_assert(U == 4, "one target per lane of a quad");
+        const int is = ((j & 3) * NG + g) * stretch + i0;
+        const bool oks = is < n;
+        const int pe = oks ? L[idx_of(is)] : 0;
+        const unsigned ts = (unsigned)pe >> 12;
+        const int uks = pe & 4095;
+        const cpx<T> vs = in[(size_t)ts * hw + (unsigned)(kw + uks)];
         double sx, sy;
-        target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
+        target_coords(D.xy, tb.cth[ts], tb.sth[ts], k, uks, sx, sy);
         const double fy = floor(sy), fx = floor(sx);
-        const int by = (int)fy, bx = (int)fx;
-        int col, r0;
-        if constexpr (LTS > 0) {
-          col = fold_rel(bx - MH + 1 - x0, M2) + j;
-          r0 = fold_rel(by - MH + 1 - y0, M1);
-        } else {
-          col = (bx - MH + 1 + j - x0) & (M2 - 1);
-          r0 = by - MH + 1 - y0;
-        }
-        if constexpr (PAIRS) {
+        const int c0s = oks ? fold_rel((int)fx - MH + 1 - x0, M2) : TS;   // TS: no target
+        const int r0s = fold_rel((int)fy - MH + 1 - y0, M1);
+        const T dxs = (T)(sx - fx), dys = (T)(sy - fy);
+        auto target = [&](auto UC) {
+          constexpr int u = decltype(UC)::value;
+          const int col = quad_bcast<u>(c0s) + j, r0 = quad_bcast<u>(r0s);
+          const T dx = quad_bcast<u>(dxs), dy = quad_bcast<u>(dys);
+          const T vx = quad_bcast<u>(vs.x), vy = quad_bcast<u>(vs.y);
           // this lane's target (valid or not, every lane takes part in the DPP exchange)
           const int h = (lane >> 3) & 1;
-          const bool valid = ok[u] && (unsigned)col < (unsigned)TS;
-          const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
-          const T pvx = wxj * v[u].x, pvy = wxj * v[u].y;
+          const bool valid = (unsigned)col < (unsigned)TS;
+          const T wxj = fg.one(dx - (T)(j + 1 - MH));
+          const T pvx = wxj * vx, pvy = wxj * vy;
           // row weights by parity, from d = delta_y: odd rows start at the centre row m - 1
           // (offset d), even rows at row m - 2 (offset d + 1); two-row ratios up and down
           T w1, dn1, up1;
-          fg.three((T)(sy - fy), w1, dn1, up1);
+          fg.three(dy, w1, dn1, up1);
           const T dn1r = dn1 * dn1 * (T)fg.e2m;   // exp(-4 beta (d + 1))
           const T w0 = w1 * dn1, up0 = up1 * (T)fg.e4p, dn0r = dn1r * (T)fg.e4m;
           // this lane keeps its own target's parity-h weights; the other half needs parity 1 - h
@@ -495,45 +497,84 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
           };
           phase(std::integral_constant<int, 0>());
           phase(std::integral_constant<int, 1>());
-        } else if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
-          const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
-          T wc, up, dn;
-          fg.seeds((T)(sy - fy), wc, up, dn);
-          const int ab = r0 * PA + col;   // cell (r0, col); row iy adds iy * PA (folded path)
-          auto add = [&](int iy, double x, double y) {
-            int a;
-            if constexpr (LTS > 0) {
-              if ((unsigned)(r0 + iy) >= (unsigned)TS) return;
-              a = ab + iy * PA;
-            } else {
-              const int row = (r0 + iy) & (M1 - 1);
-              if (row >= TS) return;
-              a = __umul24(row, PA) + col;
-            }
-            atomicAdd(are + a, x);
-            atomicAdd(aim + a, y);
-          };
-          // the column's products with the row weights, by the weight recurrence in FP64 from the
-          // centre row outwards
-          const double cx = (double)(wxj * v[u].x) * (double)wc, cy = (double)(wxj * v[u].y) * (double)wc;
-          add(MH - 1, cx, cy);
-          double px = cx, py = cy, r = (double)up;
+        };
+        target(std::integral_constant<int, 0>());
+        target(std::integral_constant<int, 1>());
+        target(std::integral_constant<int, 2>());
+        target(std::integral_constant<int, 3>());
+      } else {
+        int t[U], uk[U];
+        bool ok[U];
+        double c[U], sn[U];
+        cpx<T> v[U];
 #pragma unroll
-          for (int iy = MH; iy < W; ++iy) {
-            px *= r;
-            py *= r;
-            add(iy, px, py);
-            r *= qd;
+        for (int u = 0; u < U; ++u) {
+          const int i = (u * NG + g) * stretch + i0;
+          ok[u] = i < n;
+          const int pe = ok[u] ? L[idx_of(i)] : 0;
+          t[u] = (int)((unsigned)pe >> 12);
+          uk[u] = pe & 4095;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          c[u] = tb.cth[t[u]];
+          sn[u] = tb.sth[t[u]];
+          v[u] = in[(size_t)(unsigned)t[u] * hw + (unsigned)(kw + uk[u])];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          double sx, sy;
+          target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
+          const double fy = floor(sy), fx = floor(sx);
+          const int by = (int)fy, bx = (int)fx;
+          int col, r0;
+          if constexpr (LTS > 0) {
+            col = fold_rel(bx - MH + 1 - x0, M2) + j;
+            r0 = fold_rel(by - MH + 1 - y0, M1);
+          } else {
+            col = (bx - MH + 1 + j - x0) & (M2 - 1);
+            r0 = by - MH + 1 - y0;
           }
-          px = cx;
-          py = cy;
-          r = (double)dn;
+          if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
+            const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
+            T wc, up, dn;
+            fg.seeds((T)(sy - fy), wc, up, dn);
+            const int ab = r0 * PA + col;   // cell (r0, col); row iy adds iy * PA (folded path)
+            auto add = [&](int iy, double x, double y) {
+              int a;
+              if constexpr (LTS > 0) {
+                if ((unsigned)(r0 + iy) >= (unsigned)TS) return;
+                a = ab + iy * PA;
+              } else {
+                const int row = (r0 + iy) & (M1 - 1);
+                if (row >= TS) return;
+                a = __umul24(row, PA) + col;
+              }
+              atomicAdd(are + a, x);
+              atomicAdd(aim + a, y);
+            };
+            // the column's products with the row weights, by the weight recurrence in FP64 from the
+            // centre row outwards
+            const double cx = (double)(wxj * v[u].x) * (double)wc, cy = (double)(wxj * v[u].y) * (double)wc;
+            add(MH - 1, cx, cy);
+            double px = cx, py = cy, r = (double)up;
 #pragma unroll
-          for (int iy = MH - 2; iy >= 0; --iy) {
-            px *= r;
-            py *= r;
-            add(iy, px, py);
-            r *= qd;
+            for (int iy = MH; iy < W; ++iy) {
+              px *= r;
+              py *= r;
+              add(iy, px, py);
+              r *= qd;
+            }
+            px = cx;
+            py = cy;
+            r = (double)dn;
+#pragma unroll
+            for (int iy = MH - 2; iy >= 0; --iy) {
+              px *= r;
+              py *= r;
+              add(iy, px, py);
+              r *= qd;
+            }
           }
         }
       }
