@@ -452,26 +452,28 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
         const double fy = floor(sy), fx = floor(sx);
         const int c0s = oks ? fold_rel((int)fx - MH + 1 - x0, M2) : TS;   // TS: no target
         const int r0s = fold_rel((int)fy - MH + 1 - y0, M1);
-        const T dxs = (T)(sx - fx), dys = (T)(sy - fy);
+        const T dxs = (T)(sx - fx);
+        // row weights by parity, from d = delta_y: odd rows start at the centre row m - 1
+        // (offset d), even rows at row m - 2 (offset d + 1); two-row ratios up and down.  The
+        // group's lanes all have parity h = g & 1: keep parity h, the other half needs 1 - h.
+        const int h = g & 1;
+        T w1, dn1, up1;
+        fg.three((T)(sy - fy), w1, dn1, up1);
+        const T dn1r = dn1 * dn1 * (T)fg.e2m;   // exp(-4 beta (d + 1))
+        const T w0 = w1 * dn1, up0 = up1 * (T)fg.e4p, dn0r = dn1r * (T)fg.e4m;
+        const T wshs = h ? w1 : w0, uphs = h ? up1 : up0, dnhs = h ? dn1r : dn0r;
+        const T wsxs = h ? w0 : w1, upxs = h ? up0 : up1, dnxs = h ? dn0r : dn1r;
         auto target = [&](auto UC) {
           constexpr int u = decltype(UC)::value;
           const int col = quad_bcast<u>(c0s) + j, r0 = quad_bcast<u>(r0s);
-          const T dx = quad_bcast<u>(dxs), dy = quad_bcast<u>(dys);
+          const T dx = quad_bcast<u>(dxs);
           const T vx = quad_bcast<u>(vs.x), vy = quad_bcast<u>(vs.y);
+          const T ws_h = quad_bcast<u>(wshs), up_h = quad_bcast<u>(uphs), dn_h = quad_bcast<u>(dnhs);
+          const T ws_x = quad_bcast<u>(wsxs), up_x = quad_bcast<u>(upxs), dn_x = quad_bcast<u>(dnxs);
           // this lane's target (valid or not, every lane takes part in the DPP exchange)
-          const int h = (lane >> 3) & 1;
           const bool valid = (unsigned)col < (unsigned)TS;
           const T wxj = fg.one(dx - (T)(j + 1 - MH));
           const T pvx = wxj * vx, pvy = wxj * vy;
-          // row weights by parity, from d = delta_y: odd rows start at the centre row m - 1
-          // (offset d), even rows at row m - 2 (offset d + 1); two-row ratios up and down
-          T w1, dn1, up1;
-          fg.three(dy, w1, dn1, up1);
-          const T dn1r = dn1 * dn1 * (T)fg.e2m;   // exp(-4 beta (d + 1))
-          const T w0 = w1 * dn1, up0 = up1 * (T)fg.e4p, dn0r = dn1r * (T)fg.e4m;
-          // this lane keeps its own target's parity-h weights; the other half needs parity 1 - h
-          const T ws_h = h ? w1 : w0, up_h = h ? up1 : up0, dn_h = h ? dn1r : dn0r;
-          const T ws_x = h ? w0 : w1, up_x = h ? up0 : up1, dn_x = h ? dn0r : dn1r;
           const int col_o = valid ? col : TS;
           // target of the row's first half, then of its second half
           auto phase = [&](auto H) {
