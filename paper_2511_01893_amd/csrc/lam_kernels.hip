@@ -54,7 +54,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
                                                Tables<T> tb, int log2TX_, int y0, size_t in_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int log2TX = LN > 0 ? LB : log2TX_, log2M0 = LN > 0 ? LN : D.log2M0;
-  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = D.n0;
+  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // blockIdx.y is the row within the input slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -73,6 +73,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
     cpx<T> v[vpt<T>()];
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (it * nth >= n0 * TX) break;   // the input fills n0 of the M0 rows
       const int e = min(tid + it * nth, n0 * TX - 1);    // clamped: every load is issued unconditionally
       const int a = e >> log2TX, b = e & (TX - 1);
       const size_t gi = (size_t)a * in_zs + (size_t)yl * D.n2 + x0 + b;
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (it * nth >= n0 * TX) break;
       const int e = tid + it * nth;
       if (e < n0 * TX) {
         const int a = e >> log2TX, b = e & (TX - 1);
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
                                                Tables<T> tb, int log2TX_, int y0, size_t out_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int log2TX = LN > 0 ? LB : log2TX_, log2M0 = LN > 0 ? LN : D.log2M0;
-  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = D.n0;
+  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // blockIdx.y is the row within the output slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -137,12 +139,14 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     cpx<T> g[vpt<T>()];
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (e0 + it * nth >= D.h * TX) break;
       const int e = min(e0 + tid + it * nth, D.h * TX - 1);
       const int av = e >> log2TX, b = e & (TX - 1);
       g[it] = u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b];
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (e0 + it * nth >= D.h * TX) break;
       const int e = e0 + tid + it * nth;
       if (e < D.h * TX) buf[e] = conj(g[it]);
     }
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
                                                    Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
-  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = D.n1, n2 = D.n2;
+  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
@@ -208,11 +212,13 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
     cpx<T> v[vpt<T>()];
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (it * nth >= n1 * TX) break;   // the input fills n1 of the M1 rows
       const int e = min(tid + it * nth, n1 * TX - 1);
       v[it] = u1[((size_t)k * n1 + (e >> log2TX)) * n2 + x0 + (e & (TX - 1))];
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (it * nth >= n1 * TX) break;
       const int e = tid + it * nth;
       if (e < n1 * TX) {
         const int a = e >> log2TX, b = e & (TX - 1);
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
                                                    Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
-  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = D.n1, n2 = D.n2;
+  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
@@ -273,11 +279,13 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
     cpx<T> v[vpt<T>()];
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (it * nth >= RB * n2) break;   // the input fills n2 of the M2 points of each row
       const int e = min(tid + it * nth, RB * n2 - 1);
       v[it] = Tb[r0 * n2 + e];
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
+      if (it * nth >= RB * n2) break;
       const int e = tid + it * nth;
       if (e < RB * n2) {
         const int b = e >> log2n2, a = e & (n2 - 1);
