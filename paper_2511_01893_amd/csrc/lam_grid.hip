@@ -15,7 +15,10 @@
 //   k_scatter  accumulates one tile in LDS in FP64: its own list plus the
 //              border classes of the 8 neighbouring tiles whose stencils
 //              reach in, one lane per stencil column, one FP64 LDS atomic per
-//              stencil row.  Every cell of the tile is then written once.
+//              stencil row (for m = 4 on large grids laid out so that each
+//              atomic instruction adds two adjacent rows of 4 targets, which
+//              spreads it evenly over the LDS banks).  Every cell of the tile
+//              is then written once.
 #include <type_traits>
 
 #include "lam_internal.hpp"
