@@ -81,7 +81,11 @@ def test_tiny32_all_entry_points(L, dtype):
     dict(n0=32, n1=32, n2=32, ntheta=12, phi=20.0, h=32, w=32, m=2),
     dict(n0=32, n1=32, n2=32, ntheta=12, phi=60.0, h=32, w=32, m=8),
     dict(n0=32, n1=32, n2=32, ntheta=9, phi=25.0, h=32, w=32, slab=3),  # ragged last slab
-], ids=["rect", "ragged-theta", "m1", "m2", "m8-phi60", "slab3"])
+    # grids of at least 128 x 128 take the 64 x 64 tile kernels with folded tile positions (and,
+    # for complex64, the row-pair spread): a rectangular grid of 2 x 4 tiles, a non-square detector
+    dict(n0=32, n1=64, n2=128, ntheta=21, phi=40.0, h=64, w=128),
+    dict(n0=16, n1=128, n2=64, ntheta=11, phi=15.0, h=16, w=32, slab=5),  # ragged slabs on 4 x 2 tiles
+], ids=["rect", "ragged-theta", "m1", "m2", "m8-phi60", "slab3", "rect-tiles", "tiles-slab5"])
 def test_geometries(L, dtype, case):
     c = dict(case)
     m, slab = c.pop("m", 4), c.pop("slab", 0)
