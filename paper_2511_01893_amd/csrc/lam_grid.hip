@@ -333,8 +333,9 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
   const int beg = of[0], end = of[9];
   const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
   // one lane per target; consecutive lanes take neighbouring targets of a run along a line, and each
-  // lane takes UG targets per step whose loads are in flight together
-  constexpr int UG = 2;
+  // lane takes UG targets per step whose loads are in flight together (complex128 keeps two: four
+  // would take it past 128 registers)
+  constexpr int UG = sizeof(T) == 4 ? 4 : 2;
   for (int i0 = beg + tid; i0 < end; i0 += UG * nth) {
     int t[UG], uk[UG];
     double c[UG], sn[UG];
