@@ -175,7 +175,7 @@ def main():
                     help="also run one plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the operator runs on one GPU: --gpus must be 1 (the sharded design is described, not built)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
