@@ -383,9 +383,22 @@ def lsp(u, psi, lam, rho, dhat, g: Geometry, n_inner: int):
     return u
 
 
+def penalty_update(rho: float, r: float, s: float) -> float:
+    """Residual balancing (Boyd et al. 2011, Section 3.4.1; the paper names rho
+    and the residuals r, s only): double rho when the primal residual r exceeds
+    ten times the dual residual s, halve it in the opposite case."""
+    if r > 10.0 * s:
+        return rho * 2.0
+    if s > 10.0 * r:
+        return rho * 0.5
+    return rho
+
+
 def admm_step(u, psi, lam, rho, dhat, g: Geometry, alpha: float, n_inner: int):
-    """One ADMM-TV iteration: LSP, RSP (isotropic shrink), multiplier update,
-    residual-balanced penalty update (factor 2, balance ratio 10)."""
+    """One ADMM-TV iteration (Equation 1; Algorithm 2's LSP, then the RSP, the
+    multiplier update and the penalty update): LSP, isotropic shrink of
+    grad u + lambda/rho, lambda += rho (grad u - psi), and residual balancing
+    with r = |grad u - psi| and s = rho |grad^T (psi - psi_prev)|."""
     u = lsp(u, psi, lam, rho, dhat, g, n_inner)
     gu = grad3(u)
     psi_prev = psi
@@ -393,11 +406,7 @@ def admm_step(u, psi, lam, rho, dhat, g: Geometry, alpha: float, n_inner: int):
     lam = lam + rho * (gu - psi)
     r = np.linalg.norm(gu - psi)
     s = rho * np.linalg.norm(grad3_adj(psi - psi_prev))
-    if r > 10.0 * s:
-        rho = rho * 2.0
-    elif s > 10.0 * r:
-        rho = rho * 0.5
-    return u, psi, lam, rho
+    return u, psi, lam, penalty_update(rho, r, s)
 
 
 def relerr(x: np.ndarray, ref: np.ndarray) -> float:

@@ -290,3 +290,84 @@ def test_phantom_is_deterministic():
     u = I.blob_phantom((32, 32, 32), bl)
     assert set(np.unique(bl.cube_values)) <= {0.0, 0.5, 1.0}
     assert u.min() >= 0
+
+
+# ---------------------------------------------------------------- ADMM update pins (Equation 1)
+def _admm_tiny(seed=5):
+    g = O.Geometry(8, 8, 8, 6, 30 * DEG, 8, 8, 2, 4)
+    u_true = I.blob_phantom(g.vol_shape, I.draw_blobs(seed, 3))
+    dhat = O.f2d_unnorm(O.lam_fwd(u_true, g).real.astype(complex))
+    return g, dhat
+
+
+def _data_grad(u, dhat, g):
+    return O.lam_adj_hat(O.lam_fwd_hat(u, g, dhat), g).real / (g.h * g.w)
+
+
+def test_admm_lsp_stationarity_after_exact_solve():
+    """Optimality of the u-update (the LSP of Equation 1 solved exactly by many CG
+    steps), rewritten with the updated multiplier lambda' = lambda + rho (grad u - psi'):
+        Re L^*(L^ u - d^)/(h w) + grad^T lambda' + rho grad^T (psi' - psi) = 0.
+    A wrong sign of the TV term in the LSP gradient, of the multiplier update or
+    of the data term breaks it."""
+    g, dhat = _admm_tiny()
+    rng = np.random.default_rng(6)
+    psi = 0.05 * rng.standard_normal((3,) + g.vol_shape)
+    lam = 0.02 * rng.standard_normal((3,) + g.vol_shape)
+    u0 = 0.1 * rng.standard_normal(g.vol_shape)
+    rho, alpha = 0.7, 2e-3
+    u, psi1, lam1, _ = O.admm_step(u0, psi, lam, rho, dhat, g, alpha, 300)
+    gd = _data_grad(u, dhat, g)
+    res = gd + O.grad3_adj(lam1) + rho * O.grad3_adj(psi1 - psi)
+    scale = np.linalg.norm(gd) + np.linalg.norm(O.grad3_adj(lam1))
+    assert np.linalg.norm(res) < 1e-8 * scale, np.linalg.norm(res) / scale
+    # the same residual with the multiplier update's sign flipped is far from zero
+    lam_bad = lam - rho * (O.grad3(u) - psi1)
+    bad = gd + O.grad3_adj(lam_bad) + rho * O.grad3_adj(psi1 - psi)
+    assert np.linalg.norm(bad) > 1e-3 * scale
+
+
+def test_admm_multiplier_is_subgradient_of_tv():
+    """After every ADMM step the multiplier lies in alpha times the subdifferential of
+    the isotropic TV norm at psi' (the psi-subproblem's optimality condition):
+    lambda'_v = alpha psi'_v/|psi'_v| where psi'_v != 0, and |lambda'_v| <= alpha where
+    psi'_v = 0.  alpha is chosen so that both cases occur."""
+    g, dhat = _admm_tiny()
+    u = np.zeros(g.vol_shape)
+    psi = np.zeros((3,) + g.vol_shape)
+    lam = np.zeros_like(psi)
+    rho, alpha = 0.5, 4e-3
+    for it in range(3):
+        u, psi, lam, rho = O.admm_step(u, psi, lam, rho, dhat, g, alpha, 4)
+        nrm = np.sqrt((psi ** 2).sum(0))
+        lnrm = np.sqrt((lam ** 2).sum(0))
+        nz = nrm > 0
+        assert 0 < nz.sum() < nz.size, (it, nz.sum())
+        np.testing.assert_allclose(lam[:, nz], alpha * psi[:, nz] / nrm[nz], rtol=0, atol=1e-12 * alpha)
+        assert np.all(lnrm[~nz] <= alpha * (1 + 1e-12))
+
+
+def test_penalty_update_branches():
+    """Residual balancing: rho doubles when r > 10 s, halves when s > 10 r, else stays."""
+    assert O.penalty_update(1.0, 10.5, 1.0) == 2.0
+    assert O.penalty_update(1.0, 1.0, 10.5) == 0.5
+    assert O.penalty_update(1.0, 10.0, 1.0) == 1.0       # the rule's inequalities are strict
+    assert O.penalty_update(1.0, 1.0, 10.0) == 1.0
+    assert O.penalty_update(0.25, 3.0, 2.0) == 0.25
+
+
+def test_admm_penalty_direction_in_constructed_states():
+    """States that force each branch inside admm_step: with alpha so large that the shrink
+    returns psi' = 0 from psi = 0, the dual residual is 0 and the primal one |grad u| > 0,
+    so rho must double; with alpha = 0 and lambda = 0 the shrink returns psi' = grad u, the
+    primal residual is 0 and the dual one rho |grad^T grad u| > 0, so rho must halve."""
+    g, dhat = _admm_tiny()
+    zero_u = np.zeros(g.vol_shape)
+    zero_p = np.zeros((3,) + g.vol_shape)
+    u, psi, lam, rho = O.admm_step(zero_u, zero_p, zero_p, 0.5, dhat, g, 1e9, 3)
+    assert np.all(psi == 0) and np.linalg.norm(O.grad3(u)) > 0
+    assert rho == 1.0
+    u, psi, lam, rho = O.admm_step(zero_u, zero_p, zero_p, 0.5, dhat, g, 0.0, 3)
+    np.testing.assert_allclose(psi, O.grad3(u), rtol=0, atol=1e-15)
+    assert np.all(lam == 0)
+    assert rho == 0.25
