@@ -202,7 +202,10 @@ int lam_profile(lam_plan p, int on);
 int lam_profile_read(lam_plan p, double* total_ms, long long* launches);
 const char* lam_kernel_name(int k);
 
-/* Release the plan (host memory only; the workspace stays the caller's). */
+/* Release the plan (host memory only; the workspace stays the caller's).  Waits
+ * for the copies of host-streamed calls still in flight on the plan's copy
+ * stream; kernels already enqueued on the caller's streams keep reading the
+ * workspace, so the caller must not free it before those streams finish. */
 void lam_destroy(lam_plan p);
 
 /* Static text for a status code. */

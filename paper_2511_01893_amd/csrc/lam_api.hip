@@ -71,7 +71,11 @@ struct lam_plan_s {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : {ev_ready[0], ev_ready[1], ev_freed[0], ev_freed[1], ev_start, ev_done})
       if (e) (void)hipEventDestroy(e);
-    if (copy) (void)hipStreamDestroy(copy);
+    // copies of a streamed call may still be in flight on the plan's copy stream
+    if (copy) {
+      (void)hipStreamSynchronize(copy);
+      (void)hipStreamDestroy(copy);
+    }
   }
 };
 
@@ -407,6 +411,23 @@ int build_lists(lam_plan_s* P) {
                               "target fill");
     if (rc) return rc;
   }
+  // exact check: one bit per target in the (still unused) data buffer, a violation counter after it
+  const size_t nbits = (size_t)h * P->p.ntheta * P->p.w, words = (nbits + 31) / 32;
+  unsigned* seen = reinterpret_cast<unsigned*>(P->ws + P->off_p);
+  int* bad = reinterpret_cast<int*>(seen + words);
+  e = hipMemset(seen, 0, words * sizeof(unsigned) + sizeof(int));
+  if (e != hipSuccess) return hip_status(e, "target check clear");
+  for (int k0 = 0; k0 < h; k0 += chunk) {
+    const int rc = hip_status(launch_list_check<T>(P->cfg, k0, std::min(chunk, h - k0), P->D, tb, seen, bad, nullptr),
+                              "target check");
+    if (rc) return rc;
+  }
+  int nbad = 0;
+  e = hipMemcpy(&nbad, bad, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(e, "target check copy");
+  if (nbad)
+    return fail(LAM_ERR_STATE, "target lists: " + std::to_string(nbad) +
+                                   " entries out of range, misfiled or listed twice");
   return hip_status(hipDeviceSynchronize(), "target list build");
 }
 

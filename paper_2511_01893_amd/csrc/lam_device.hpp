@@ -272,7 +272,7 @@ struct XYGeom {
 // Contraction is off so the coordinate is the plain sequence of correctly
 // rounded products and sums: at angles where s lands on an integer (multiples
 // of pi/2), a fused multiply-add would round differently and move floor(s).
-__device__ __forceinline__ void target_coords(const XYGeom& g, double ct, double st, int akv, int aku,
+__host__ __device__ inline void target_coords(const XYGeom& g, double ct, double st, int akv, int aku,
                                               double& sx, double& sy) {
 #pragma clang fp contract(off)
   const double ku = (double)(aku - g.w / 2) * g.inv_w;

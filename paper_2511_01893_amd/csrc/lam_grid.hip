@@ -21,61 +21,13 @@
 //              is then written once.
 #include <type_traits>
 
-#include "lam_internal.hpp"
+#include "lam_lists.hpp"
 
 namespace lam {
 
 extern __shared__ __align__(16) unsigned char lam_smem[];
 
 namespace {
-
-// k_u interval(s) of one angle's targets whose floor(s) lies, modulo M, in
-// [X0, X0 + LX) along one axis; s = A k_u + B.  At most two intervals (the
-// line meets the periodic images of a band only near its ends).  Bounds are
-// generous; callers re-check every candidate exactly.
-__device__ __forceinline__ void interval_1d(double A, double iA, double B, double lo_s, double hi_s, int kmin,
-                                            int kmax, int& a, int& b) {
-  if (iA == 0.0) {
-    if (B >= lo_s - 1.0 && B < hi_s + 1.0) { a = kmin; b = kmax; }
-    else { a = 1; b = 0; }
-    return;
-  }
-  double k1 = (lo_s - B) * iA, k2 = (hi_s - B) * iA;
-  if (k1 > k2) { const double t = k1; k1 = k2; k2 = t; }
-  k1 = fmax(k1, (double)kmin - 2.0);
-  k2 = fmin(k2, (double)kmax + 2.0);
-  a = max(kmin, (int)ceil(k1 - 1e-3));
-  b = min(kmax, (int)floor(k2 + 1e-3));
-}
-
-__device__ __forceinline__ int axis_intervals(double A, double iA, double B, int X0, int LX, int M, int kmin, int kmax,
-                                              int* lo, int* hi) {
-  const double half = fabs(A) * (double)(kmax - kmin) * 0.5 + fabs(A);
-  const double mid = B + A * 0.5 * (double)(kmin + kmax);
-  const double smin = mid - half - 1.0, smax = mid + half + 1.0;
-  int n = 0;
-  for (int i = -2; i <= 2; ++i) {
-    const double l = (double)X0 + (double)i * M, h = l + LX;
-    if (h < smin || l > smax) continue;
-    int a, b;
-    interval_1d(A, iA, B, l, h, kmin, kmax, a, b);
-    if (a > b) continue;
-    if (n < 2) { lo[n] = a; hi[n] = b; ++n; }
-    else { lo[1] = min(lo[1], a); hi[1] = max(hi[1], b); }
-  }
-  // the generous bounds let the intervals of neighbouring images overlap when
-  // the band spans most of the period; visit their union so no k_u comes twice
-  if (n == 2 && lo[1] <= hi[0] + 1 && lo[0] <= hi[1] + 1) {
-    lo[0] = min(lo[0], lo[1]);
-    hi[0] = max(hi[0], hi[1]);
-    n = 1;
-  }
-  return n;
-}
-
-__device__ __forceinline__ int border_class(int o, int TS, int MH) {
-  return o < MH - 1 ? 0 : (o >= TS - MH ? 2 : 1);
-}
 
 // Visit every target of slice k whose base row lies in the band of tile row
 // ty.  One wave per angle; its lanes take consecutive k_u, so each call of
@@ -85,29 +37,17 @@ __device__ __forceinline__ int border_class(int o, int TS, int MH) {
 template <int MH, class F>
 __device__ __forceinline__ void band_targets(const Dims& D, const double* cth, const double* sth, const double* line,
                                              int k, int ty, int log2TS, F&& f) {
-  const int TS = 1 << log2TS, M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
-  const int Y0 = ty * TS;
-  const int kmin = -D.w / 2, kmax = D.w / 2 - 1;
-  const double kv = (double)(k - D.h / 2) * D.xy.inv_h;
+  const int Y0 = ty << log2TS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   for (int t = wave; t < D.ntheta; t += nwave) {
-    const double* ln = line + 6 * t;
     int lo[2], hi[2];
-    const int n = axis_intervals(ln[3], ln[4], ln[5] * kv, Y0, TS, M1, kmin, kmax, lo, hi);
+    const int n = band_intervals(D, line + 6 * t, k, Y0, log2TS, lo, hi);
     for (int jj = 0; jj < n; ++jj)
       for (int ku0 = lo[jj]; ku0 <= hi[jj]; ku0 += 64) {
         const int ku = ku0 + lane;
         bool ok = ku <= hi[jj];
         int tx = 0, c = 0;
-        if (ok) {
-          double sx, sy;
-          target_coords(D.xy, cth[t], sth[t], k, ku + D.w / 2, sx, sy);
-          const int oy = ((int)floor(sy) - Y0) & (M1 - 1);
-          const int fx = (int)floor(sx) & (M2 - 1);
-          ok = oy < TS;
-          tx = fx >> log2TS;
-          c = border_class(oy, TS, MH) * 3 + border_class(fx & (TS - 1), TS, MH);
-        }
+        if (ok) ok = classify_target(D, cth[t], sth[t], k, ku + D.w / 2, Y0, log2TS, MH, tx, c);
         f(ok, t, ku + D.w / 2, tx, c);
       }
   }
@@ -162,6 +102,33 @@ __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log
       pending &= ~m;
     }
   });
+}
+
+// Exact check of the lists of slices [k0, k0 + gridDim.y), one block per (tile, slice): every entry
+// must name a target in range, classify (by the same FP64 coordinates) into the tile and border
+// class whose list holds it, and appear only once in its slice (a bit per target in `seen`, cleared
+// by the caller).  With the per-slice counts equal to n_theta w this makes each slice's lists a
+// permutation of its targets.  Every violation adds one to *bad.
+template <typename T, int MH>
+__global__ __launch_bounds__(256) void k_list_check(Dims D, Tables<T> tb, int log2TS, int k0,
+                                                    unsigned* __restrict__ seen, int* __restrict__ bad) {
+  const int ntx = (1 << D.log2M2) >> log2TS, nty = (1 << D.log2M1) >> log2TS;
+  const int tile = blockIdx.x, k = k0 + blockIdx.y, tx = tile % ntx, ty = tile / ntx;
+  const int* of = tb.toff + (size_t)k * ((size_t)ntx * nty * 9 + 1) + (size_t)tile * 9;
+  const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
+  int nbad = 0;
+  for (int c = 0; c < 9; ++c)
+    for (int i = of[c] + (int)threadIdx.x; i < of[c + 1]; i += blockDim.x) {
+      const int id = L[i], t = id >> 12, aku = id & 4095;
+      if (id < 0 || t >= D.ntheta || aku >= D.w) { ++nbad; continue; }
+      int tx2 = -1, c2 = -1;
+      if (!classify_target(D, tb.cth[t], tb.sth[t], k, aku, ty << log2TS, log2TS, MH, tx2, c2) || tx2 != tx || c2 != c)
+        ++nbad;
+      const size_t bit = ((size_t)k * D.ntheta + t) * D.w + aku;
+      const unsigned m = 1u << (bit & 31);
+      if (atomicOr(&seen[bit >> 5], m) & m) ++nbad;
+    }
+  if (nbad) atomicAdd(bad, nbad);
 }
 
 }  // namespace
@@ -655,6 +622,17 @@ hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, c
 }
 
 template <typename T>
+hipError_t launch_list_check(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, unsigned* seen,
+                             int* bad, hipStream_t s) {
+  const int ntx = (1 << D.log2M2) >> c.g_log2TS, nty = (1 << D.log2M1) >> c.g_log2TS;
+  LAM_MH_SWITCH(D.m, {
+    hipLaunchKernelGGL((k_list_check<T, MH>), dim3(ntx * nty, ns), dim3(256), 0, s, D, tb, c.g_log2TS, k0, seen,
+                       bad);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_gather(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* out, const cpx<T>* dhat, int k0, int ns,
                          const Dims& D, const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
@@ -672,7 +650,9 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
                           const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
-    auto k = MH == 4 && fast_tiles(c, D) ? k_scatter<T, MH, 6, MH == 4> : k_scatter<T, MH>;
+    auto k = k_scatter<T, MH>;
+    if constexpr (MH == 4)
+      if (fast_tiles(c, D)) k = k_scatter<T, MH, 6, true>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
     const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
     hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
@@ -684,6 +664,8 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
   template hipError_t launch_list_count<T>(const LaunchCfg&, int, int, const Dims&, const Tables<T>&, int*,       \
                                            hipStream_t);                                                         \
   template hipError_t launch_list_fill<T>(const LaunchCfg&, int, int, const Dims&, const Tables<T>&, const int*,  \
+                                          int*, hipStream_t);                                                    \
+  template hipError_t launch_list_check<T>(const LaunchCfg&, int, int, const Dims&, const Tables<T>&, unsigned*, \
                                           int*, hipStream_t);                                                    \
   template hipError_t launch_gather<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, const cpx<T>*, int, int,        \
                                        const Dims&, const Tables<T>&, hipStream_t);                              \

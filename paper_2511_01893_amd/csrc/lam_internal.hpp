@@ -113,6 +113,9 @@ template <typename T>
 hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, const int* offs,
                             int* lists, hipStream_t s);
 template <typename T>
+hipError_t launch_list_check(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, unsigned* seen,
+                             int* bad, hipStream_t s);
+template <typename T>
 hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, int nproj, const Dims& D,
                          const Tables<T>& tb, hipStream_t s);
 template <typename T>

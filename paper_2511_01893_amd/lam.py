@@ -122,6 +122,7 @@ class Plan:
         self._h = c_void_p()
         _check(lib().lam_init(byref(self._h), byref(p)))
         nbytes = lib().lam_workspace_bytes(self._h)
+        self._home = torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _check(lib().lam_set_workspace(self._h, c_void_p(self.workspace.data_ptr()), nbytes))
 
@@ -140,8 +141,16 @@ class Plan:
     def data_shape(self):
         return (self.ntheta, self.h, self.w)
 
-    def _stream(self):
-        return c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+    def _stream(self, *tensors):
+        """The calling stream; the workspace (and `tensors`, device scratch of the caller) are
+        marked as used on it, so the caching allocator does not hand their memory out again
+        while work of this call is pending on a stream other than the one they came from."""
+        s = torch.cuda.current_stream(self.device)
+        if s != self._home:
+            self.workspace.record_stream(s)
+            for t in tensors:
+                t.record_stream(s)
+        return c_void_p(s.cuda_stream)
 
     def _arr(self, x: torch.Tensor, shape, what: str, allow_real=False) -> torch.Tensor:
         if tuple(x.shape) != tuple(shape):
@@ -314,7 +323,7 @@ class AdmmTV:
                        c_void_p(self.work.data_ptr()),
                        ctypes.cast(c_void_p(self.scal.data_ptr()), POINTER(c_double)))
         _check(lib().lam_admm_step(self.plan._h, byref(st), c_void_p(dhat.data_ptr()), n_inner,
-                                   self.plan._stream()))
+                                   self.plan._stream(self.work)))
 
 
 def admm_tv(plan: Plan, d: torch.Tensor, alpha: float, n_outer: int = 4, n_inner: int = 4,

@@ -114,7 +114,31 @@ def test_lam1024_slabs_of_128(L):
     e_a = rel(Lsd.double(), p128.adj(d.to(torch.complex128), real=True))
     print(f"1024^3 c64 vs c128: fwd {e_f:.2e} adj {e_a:.2e}")
     assert e_f < 1e-4 and e_a < 1e-4
-    del p128
+    # central differences at 16 random voxels (seed 304) of 1/2 |L u - d|^2 evaluated through the
+    # complex128 plan (a complex64 loss at this size cannot resolve one voxel), against the complex64
+    # autograd gradient (backward = the adjoint kernel); the loss is quadratic, so the central
+    # difference is the directional derivative up to FP64 rounding
+    ug = u.clone().requires_grad_(True)
+    (0.5 * (L.LamOp.apply(ug, p64) - d).abs().pow(2).sum()).backward()
+    g64 = ug.grad.detach()
+    d128 = d.to(torch.complex128)
+    ud = u.double()
+
+    def loss128(x):
+        r = p128.fwd(x) - d128
+        return 0.5 * float((r.real ** 2 + r.imag ** 2).sum())
+
+    idx = np.random.default_rng(304).integers(0, u.numel(), 16)
+    eps, gmax, worst = 0.5, g64.abs().max().item(), 0.0
+    for i in idx:
+        e = torch.zeros(u.numel(), dtype=torch.float64, device="cuda")
+        e[int(i)] = eps
+        e = e.view_as(ud)
+        fd = (loss128(ud + e) - loss128(ud - e)) / (2 * eps)
+        worst = max(worst, abs(fd - g64.view(-1)[int(i)].item()) / gmax)
+    print(f"1024^3 finite differences at 16 voxels (complex128 loss): worst error / max |grad| {worst:.2e}")
+    assert worst < 1e-3
+    del p128, d128, ud, e
     torch.cuda.empty_cache()
     # directional finite differences of 1/2 |L u - d|^2 along whole-volume directions (one voxel
     # moves a 1024^3 loss by less than its complex64 rounding): the loss is quadratic, so the central

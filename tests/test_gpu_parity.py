@@ -85,7 +85,11 @@ def test_tiny32_all_entry_points(L, dtype):
     # for complex64, the row-pair spread): a rectangular grid of 2 x 4 tiles, a non-square detector
     dict(n0=32, n1=64, n2=128, ntheta=21, phi=40.0, h=64, w=128),
     dict(n0=16, n1=128, n2=64, ntheta=11, phi=15.0, h=16, w=32, slab=5),  # ragged slabs on 4 x 2 tiles
-], ids=["rect", "ragged-theta", "m1", "m2", "m8-phi60", "slab3", "rect-tiles", "tiles-slab5"])
+    # other half-widths on several tiles: the general spread with the neighbours' border classes, 16-lane
+    # groups for m = 8 and 8-lane groups for m = 3
+    dict(n0=32, n1=128, n2=64, ntheta=13, phi=30.0, h=32, w=64, m=8),
+    dict(n0=32, n1=64, n2=128, ntheta=17, phi=45.0, h=32, w=128, m=3),
+], ids=["rect", "ragged-theta", "m1", "m2", "m8-phi60", "slab3", "rect-tiles", "tiles-slab5", "m8-tiles", "m3-tiles"])
 def test_geometries(L, dtype, case):
     c = dict(case)
     m, slab = c.pop("m", 4), c.pop("slab", 0)
