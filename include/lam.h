@@ -189,6 +189,27 @@ size_t lam_admm_work_bytes(lam_plan p);
  * Enqueues work only; no host synchronisation. */
 int lam_admm_step(lam_plan p, const lam_admm_state* s, const void* dhat, int n_inner, void* hip_stream);
 
+/* d = L u as lam_fwd, with no workspace and no allocation: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The plan's tables, target lists
+ * and stage buffers live in a static device array of LAM_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends; the plan
+ * needs no lam_set_workspace for this call.  The caller passes u (complex
+ * (n0, n1, n2)) and d (complex (ntheta, h, w)) as for lam_fwd; the result is
+ * the same as lam_fwd's.
+ * The array of a GPU is shared by every call on it and keeps the last call's
+ * contents: the first call of a plan on a GPU (and the first after another
+ * plan's call there) synchronises the device and rebuilds the plan's tables
+ * and target lists in it (host-to-device copies and list kernels on the null
+ * stream); later calls of the same plan only enqueue on hip_stream.  Calls
+ * that overlap in time on one GPU (other threads, other streams, other plans)
+ * race on the array.  No hipMalloc, hipFree or allocating library call is
+ * made.  Errors: as lam_fwd; LAM_ERR_WORKSPACE when the plan needs more than
+ * LAM_SCRATCH_BYTES (lam_workspace_bytes less the host-streaming buffers;
+ * about 64^3 volumes, or larger ones with a small slab). */
+#define LAM_SCRATCH_BYTES ((size_t)64 << 20)
+int lam_fwd_scratch(lam_plan p, const void* u, void* d, void* hip_stream);
+
 /* Per-kernel timing, for measurement.  With profiling on, every kernel the
  * plan launches is bracketed by a pair of HIP events recorded on its stream
  * (this adds a small gap between kernels).  lam_profile_read waits for the

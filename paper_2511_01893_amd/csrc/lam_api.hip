@@ -11,6 +11,9 @@
 #include <new>
 #include <string>
 #include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "lam.h"
@@ -22,6 +25,7 @@ using namespace lam;
 namespace {
 
 thread_local std::string g_last_error;
+std::atomic<unsigned long long> g_next_uid{0};
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -33,13 +37,20 @@ int ilog2(long v) { int r = 0; while ((1L << r) < v) ++r; return r; }
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 constexpr size_t kLdsMax = 160 * 1024;
+constexpr size_t kScratchBytes = LAM_SCRATCH_BYTES;
 // complex values per thread per FFT stage (as the kernels are built): 16 for complex64, 8 for complex128
 int vpt_of(size_t csize) { return csize == 8 ? 16 : 8; }
 
 }  // namespace
 
+// Host buffers of the target-list build (counts and offsets, tile orders).
+struct ListHost {
+  std::vector<int> cnt, gperm, sperm, work;
+};
+
 struct lam_plan_s {
   lam_params p{};
+  unsigned long long uid = 0;  // unique per plan (lam_init), names the owner of a device's scratch
   std::vector<double> theta;
   int M0 = 0, M1 = 0, M2 = 0, Ntw = 0, slab = 0;
   double beta = 0;
@@ -48,6 +59,10 @@ struct lam_plan_s {
   std::vector<double> tw, cz, cy, cx, zdelta, cth, sth, rc, line;
   std::vector<int> zbase;
   std::vector<unsigned> zrun;
+  // the tables as the device holds them (type per dtype), at their workspace offsets
+  std::vector<std::pair<size_t, std::vector<unsigned char>>> blobs;
+  // list-build buffers kept for plans that fit the static scratch (their rebuilds allocate nothing)
+  ListHost lh;
   // workspace layout (byte offsets)
   size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zdelta = 0, off_cth = 0, off_sth = 0,
          off_rc = 0, off_line = 0, off_zrun = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
@@ -113,6 +128,14 @@ void row_cfg(int log2N, long nrows, size_t csize, int& log2RB, int& threads, siz
   log2RB = ilog2(RB);
   threads = (int)std::max<long>(64, N * RB / vp);
   lds = (size_t)N * RB * csize * 9 / 8;     // one pad slot per 8 elements (bank spreading)
+}
+
+template <typename T>
+std::vector<unsigned char> pack(const std::vector<double>& v) {
+  std::vector<unsigned char> out(v.size() * sizeof(T));
+  T* o = reinterpret_cast<T*>(out.data());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+  return out;
 }
 
 int build(lam_plan_s* P) {
@@ -233,6 +256,37 @@ int build(lam_plan_s* P) {
     P->off_stage = take(2 * P->stage_bytes);
   }
   P->ws_need = o;
+  // the tables as the device holds them (FP32 or FP64 per dtype where the kernels read T)
+  {
+    const bool f = p.dtype == LAM_C64;
+    auto real = [&](const std::vector<double>& v) { return f ? pack<float>(v) : pack<double>(v); };
+    auto ints = [](const void* src, size_t bytes) {
+      std::vector<unsigned char> b(bytes);
+      std::memcpy(b.data(), src, bytes);
+      return b;
+    };
+    P->blobs.clear();
+    P->blobs.emplace_back(P->off_tw, real(P->tw));
+    P->blobs.emplace_back(P->off_cz, real(P->cz));
+    P->blobs.emplace_back(P->off_cy, real(P->cy));
+    P->blobs.emplace_back(P->off_cx, real(P->cx));
+    P->blobs.emplace_back(P->off_zdelta, real(P->zdelta));
+    P->blobs.emplace_back(P->off_cth, pack<double>(P->cth));
+    P->blobs.emplace_back(P->off_sth, pack<double>(P->sth));
+    P->blobs.emplace_back(P->off_rc, pack<double>(P->rc));
+    P->blobs.emplace_back(P->off_line, pack<double>(P->line));
+    P->blobs.emplace_back(P->off_zbase, ints(P->zbase.data(), P->zbase.size() * sizeof(int)));
+    P->blobs.emplace_back(P->off_zrun, ints(P->zrun.data(), P->zrun.size() * sizeof(unsigned)));
+  }
+  // plans that fit the static scratch keep their list-build buffers, so that rebuilding the
+  // lists there (lam_fwd_scratch) allocates nothing
+  if (P->off_stage <= kScratchBytes) {
+    const size_t ntiles = (size_t)P->ntx * P->nty;
+    P->lh.cnt.resize((size_t)p.h * (ntiles * 9 + 1));
+    P->lh.gperm.resize((size_t)p.h * ntiles);
+    P->lh.sperm.resize((size_t)p.h * ntiles);
+    P->lh.work.resize(ntiles);
+  }
   // kernel dimensions
   Dims& D = P->D;
   D.n0 = p.n0; D.n1 = p.n1; D.n2 = p.n2; D.h = p.h; D.w = p.w; D.ntheta = p.ntheta; D.m = m;
@@ -274,9 +328,8 @@ int build(lam_plan_s* P) {
 }
 
 template <typename T>
-Tables<T> tables(const lam_plan_s* P) {
+Tables<T> tables(const lam_plan_s* P, const unsigned char* w) {
   Tables<T> t;
-  unsigned char* w = P->ws;
   t.tw = reinterpret_cast<const cpx<T>*>(w + P->off_tw);
   t.log2tw = ilog2(P->Ntw);
   t.cz = reinterpret_cast<const T*>(w + P->off_cz);
@@ -295,21 +348,16 @@ Tables<T> tables(const lam_plan_s* P) {
   t.zrun = reinterpret_cast<const unsigned*>(w + P->off_zrun);
   return t;
 }
-
 template <typename T>
-std::vector<unsigned char> pack(const std::vector<double>& v) {
-  std::vector<unsigned char> out(v.size() * sizeof(T));
-  T* o = reinterpret_cast<T*>(out.data());
-  for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
-  return out;
-}
+Tables<T> tables(const lam_plan_s* P) { return tables<T>(P, P->ws); }
 
 // Sort every slice's targets into per-tile lists on the device (once per
 // workspace): count per (slice, tile, border class), exclusive scan on the
 // host with the invariant that each slice lists exactly n_theta w targets,
-// then fill.  Runs on the null stream and waits for it.
+// then fill.  Runs on the null stream and waits for it.  ws: the device base
+// holding the plan's layout; lh: host buffers (sized here on first use).
 template <typename T>
-int build_lists(lam_plan_s* P);
+int build_lists(lam_plan_s* P, unsigned char* ws, ListHost& lh);
 
 int hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return LAM_OK;
@@ -353,10 +401,10 @@ int timed(lam_plan_s* P, int slot, hipStream_t s, const char* what, F&& launch) 
 double inv_hw(const lam_plan_s* P) { return 1.0 / ((double)P->p.h * (double)P->p.w); }
 
 template <typename T>
-int build_lists(lam_plan_s* P) {
-  const Tables<T> tb = tables<T>(P);
-  int* toff = reinterpret_cast<int*>(P->ws + P->off_toff);
-  int* tlist = reinterpret_cast<int*>(P->ws + P->off_tlist);
+int build_lists(lam_plan_s* P, unsigned char* ws, ListHost& lh) {
+  const Tables<T> tb = tables<T>(P, ws);
+  int* toff = reinterpret_cast<int*>(ws + P->off_toff);
+  int* tlist = reinterpret_cast<int*>(ws + P->off_tlist);
   const size_t per_slice = (size_t)P->ntx * P->nty * 9 + 1;
   const int h = P->p.h;
   const int chunk = 256;   // slices per launch
@@ -365,7 +413,12 @@ int build_lists(lam_plan_s* P) {
                               "target count");
     if (rc) return rc;
   }
-  std::vector<int> cnt((size_t)h * per_slice);
+  const int ntiles = P->ntx * P->nty;
+  lh.cnt.resize((size_t)h * per_slice);
+  lh.gperm.resize((size_t)h * ntiles);
+  lh.sperm.resize((size_t)h * ntiles);
+  lh.work.resize(ntiles);
+  std::vector<int>& cnt = lh.cnt;
   hipError_t e = hipMemcpy(cnt.data(), toff, cnt.size() * sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_status(e, "target count copy");
   const long expect = (long)P->p.ntheta * P->p.w;
@@ -382,29 +435,29 @@ int build_lists(lam_plan_s* P) {
   if (e != hipSuccess) return hip_status(e, "target offset copy");
   // per slice, the tiles in decreasing order of work (targets gathered, targets spread): the
   // kernels start the heaviest tiles first so that the dense tiles near the frequency origin do
-  // not form the tail of a launch
-  const int ntiles = P->ntx * P->nty;
-  std::vector<int> gperm((size_t)h * ntiles), sperm((size_t)h * ntiles), work(ntiles);
+  // not form the tail of a launch (ties in tile order)
+  std::vector<int>& work = lh.work;
+  auto heavier = [&](int a, int b) { return work[a] != work[b] ? work[a] > work[b] : a < b; };
   for (int k = 0; k < h; ++k) {
     const int* of = &cnt[(size_t)k * per_slice];
-    int* gp = &gperm[(size_t)k * ntiles];
-    int* sp = &sperm[(size_t)k * ntiles];
+    int* gp = &lh.gperm[(size_t)k * ntiles];
+    int* sp = &lh.sperm[(size_t)k * ntiles];
     for (int i = 0; i < ntiles; ++i) {
       gp[i] = sp[i] = i;
       work[i] = of[i * 9 + 9] - of[i * 9];
     }
-    std::stable_sort(gp, gp + ntiles, [&](int a, int b) { return work[a] > work[b]; });
+    std::sort(gp, gp + ntiles, heavier);
     for (int i = 0; i < ntiles; ++i) {
       int b[kSpreadSlots], en[kSpreadSlots];
       spread_ranges(of, P->ntx, P->nty, i / P->ntx, i % P->ntx, b, en);
       work[i] = 0;
       for (int j = 0; j < kSpreadSlots; ++j) work[i] += en[j] - b[j];
     }
-    std::stable_sort(sp, sp + ntiles, [&](int a, int b) { return work[a] > work[b]; });
+    std::sort(sp, sp + ntiles, heavier);
   }
-  e = hipMemcpy(P->ws + P->off_gperm, gperm.data(), gperm.size() * sizeof(int), hipMemcpyHostToDevice);
+  e = hipMemcpy(ws + P->off_gperm, lh.gperm.data(), lh.gperm.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(P->ws + P->off_sperm, sperm.data(), sperm.size() * sizeof(int), hipMemcpyHostToDevice);
+    e = hipMemcpy(ws + P->off_sperm, lh.sperm.data(), lh.sperm.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_status(e, "tile order copy");
   for (int k0 = 0; k0 < h; k0 += chunk) {
     const int rc = hip_status(launch_list_fill<T>(P->cfg, k0, std::min(chunk, h - k0), P->D, tb, toff, tlist, nullptr),
@@ -413,7 +466,7 @@ int build_lists(lam_plan_s* P) {
   }
   // exact check: one bit per target in the (still unused) data buffer, a violation counter after it
   const size_t nbits = (size_t)h * P->p.ntheta * P->p.w, words = (nbits + 31) / 32;
-  unsigned* seen = reinterpret_cast<unsigned*>(P->ws + P->off_p);
+  unsigned* seen = reinterpret_cast<unsigned*>(ws + P->off_p);
   int* bad = reinterpret_cast<int*>(seen + words);
   e = hipMemset(seen, 0, words * sizeof(unsigned) + sizeof(int));
   if (e != hipSuccess) return hip_status(e, "target check clear");
@@ -431,15 +484,26 @@ int build_lists(lam_plan_s* P) {
   return hip_status(hipDeviceSynchronize(), "target list build");
 }
 
+// Copy the plan's tables to the device base ws (synchronous).
+int upload_tables(const lam_plan_s* P, unsigned char* ws) {
+  for (auto& b : P->blobs) {
+    const hipError_t e = hipMemcpy(ws + b.first, b.second.data(), b.second.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(LAM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e));
+  }
+  return LAM_OK;
+}
+
 // ---------------------------------------------------------------- operators
+// ws: the device base holding the plan's layout (its workspace, or the static scratch)
 template <typename T>
-int run_fwd(lam_plan_s* P, const void* u, bool real_in, const void* dhat, void* out, bool to_space, hipStream_t s) {
-  const Tables<T> tb = tables<T>(P);
+int run_fwd(lam_plan_s* P, unsigned char* ws, const void* u, bool real_in, const void* dhat, void* out, bool to_space,
+            hipStream_t s) {
+  const Tables<T> tb = tables<T>(P, ws);
   const LaunchCfg& c = P->cfg;
   const Dims& D = P->D;
-  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(P->ws + P->off_u1);
-  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(P->ws + P->off_t);
-  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
+  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(ws + P->off_u1);
+  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(ws + P->off_t);
+  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(ws + P->off_g);
   cpx<T>* o = reinterpret_cast<cpx<T>*>(out);
   const cpx<T>* dh = reinterpret_cast<const cpx<T>*>(dhat);
   int rc = timed(P, K_ZFWD, s, "F_u1D",
@@ -644,8 +708,8 @@ int fwd_any(lam_plan p, const void* u, bool real_in, const void* dhat, void* out
   if (rc) return rc;
   if (!u || !out) return fail(LAM_ERR_ARG, "null array pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return p->p.dtype == LAM_C64 ? run_fwd<float>(p, u, real_in, dhat, out, to_space, s)
-                               : run_fwd<double>(p, u, real_in, dhat, out, to_space, s);
+  return p->p.dtype == LAM_C64 ? run_fwd<float>(p, p->ws, u, real_in, dhat, out, to_space, s)
+                               : run_fwd<double>(p, p->ws, u, real_in, dhat, out, to_space, s);
 }
 
 int adj_any(lam_plan p, const void* in, bool from_space, void* u, bool real_out, void* stream) {
@@ -671,6 +735,23 @@ int plan_adj_hat_real(lam_plan p, const void* r, void* u, hipStream_t s) { retur
 int set_error(int code, const char* msg) { return fail(code, msg); }
 }  // namespace lam
 
+// ---------------------------------------------------------------- static scratch
+// Device scratch of lam_fwd_scratch, for callers that cannot allocate: every GPU the library runs
+// on holds its own copy until the process ends.  In host code `scratch` is only a stand-in for the
+// symbol; its device address comes from hipGetSymbolAddress, once per device, and host code uses
+// that address only.  The slot of a device records which plan's tables and lists the array holds.
+static __device__ __align__(256) unsigned char scratch[LAM_SCRATCH_BYTES];
+
+namespace {
+struct ScratchSlot {
+  unsigned char* ptr = nullptr;   // device address of `scratch` on this device
+  unsigned long long owner = 0;   // uid of the plan whose tables and lists it holds (0: none)
+};
+constexpr int kScratchDevices = 64;
+ScratchSlot g_scratch_slot[kScratchDevices];
+std::mutex g_scratch_mu;
+}  // namespace
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -694,6 +775,7 @@ int lam_init(lam_plan* out, const lam_params* p) {
   if (!P) return fail(LAM_ERR_NOMEM, "plan allocation failed");
   try {
     P->p = *p;
+    P->uid = ++g_next_uid;
     P->theta.resize(p->ntheta);
     for (int t = 0; t < p->ntheta; ++t) {
       P->theta[t] = p->theta ? p->theta[t] : 2.0 * M_PI * (double)t / (double)p->ntheta;
@@ -718,37 +800,13 @@ int lam_set_workspace(lam_plan p, void* dev_ptr, size_t bytes) {
   if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) return fail(LAM_ERR_ARG, "workspace must be 256-byte aligned");
   if (bytes < p->ws_need) return fail(LAM_ERR_WORKSPACE, "workspace smaller than lam_workspace_bytes");
   unsigned char* w = static_cast<unsigned char*>(dev_ptr);
-  std::vector<std::pair<size_t, std::vector<unsigned char>>> blobs;
-  const bool f = p->p.dtype == LAM_C64;
-  blobs.emplace_back(p->off_tw, f ? pack<float>(p->tw) : pack<double>(p->tw));
-  blobs.emplace_back(p->off_cz, f ? pack<float>(p->cz) : pack<double>(p->cz));
-  blobs.emplace_back(p->off_cy, f ? pack<float>(p->cy) : pack<double>(p->cy));
-  blobs.emplace_back(p->off_cx, f ? pack<float>(p->cx) : pack<double>(p->cx));
-  blobs.emplace_back(p->off_zdelta, f ? pack<float>(p->zdelta) : pack<double>(p->zdelta));
-  blobs.emplace_back(p->off_cth, pack<double>(p->cth));
-  blobs.emplace_back(p->off_sth, pack<double>(p->sth));
-  blobs.emplace_back(p->off_rc, pack<double>(p->rc));
-  blobs.emplace_back(p->off_line, pack<double>(p->line));
-  {
-    std::vector<unsigned char> b(p->zbase.size() * sizeof(int));
-    std::memcpy(b.data(), p->zbase.data(), b.size());
-    blobs.emplace_back(p->off_zbase, std::move(b));
-    std::vector<unsigned char> r(p->zrun.size() * sizeof(unsigned));
-    std::memcpy(r.data(), p->zrun.data(), r.size());
-    blobs.emplace_back(p->off_zrun, std::move(r));
-  }
-  for (auto& b : blobs) {
-    const hipError_t e = hipMemcpy(w + b.first, b.second.data(), b.second.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return fail(LAM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e));
-  }
-  unsigned char* old_ws = p->ws;
+  int rc = upload_tables(p, w);
+  if (rc) return rc;
+  ListHost lh;
+  rc = p->p.dtype == LAM_C64 ? build_lists<float>(p, w, lh) : build_lists<double>(p, w, lh);
+  if (rc) return rc;
   p->ws = w;
   p->ws_bytes = bytes;
-  const int rc = p->p.dtype == LAM_C64 ? build_lists<float>(p) : build_lists<double>(p);
-  if (rc) {
-    p->ws = old_ws;
-    return rc;
-  }
   return LAM_OK;
 }
 
@@ -800,6 +858,42 @@ int lam_data_hat(lam_plan p, const void* d, void* dhat, void* stream) {
   if (!d || !dhat) return fail(LAM_ERR_ARG, "null array pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return p->p.dtype == LAM_C64 ? run_data_hat<float>(p, d, dhat, s) : run_data_hat<double>(p, d, dhat, s);
+}
+
+int lam_fwd_scratch(lam_plan p, const void* u, void* d, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(LAM_ERR_ARG, "null plan");
+  if (!u || !d) return fail(LAM_ERR_ARG, "null array pointer");
+  if (p->off_stage > kScratchBytes)
+    return fail(LAM_ERR_WORKSPACE, "the plan needs " + std::to_string(p->off_stage) +
+                                       " bytes of scratch, the static scratch holds " + std::to_string(kScratchBytes));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "device query");
+  if (dev < 0 || dev >= kScratchDevices) return fail(LAM_ERR_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  ScratchSlot& sl = g_scratch_slot[dev];
+  if (!sl.ptr) {
+    // the array's device address on this device (each device holds its own copy)
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_status(e, "scratch address");
+    sl.ptr = static_cast<unsigned char*>(ptr);
+  }
+  if (sl.owner != p->uid) {
+    // another plan's tables (or none) are in this device's scratch: let the device's pending work
+    // finish, then build this plan's tables and target lists there
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_status(e, "scratch handover");
+    sl.owner = 0;
+    int rc = upload_tables(p, sl.ptr);
+    if (!rc) rc = p->p.dtype == LAM_C64 ? build_lists<float>(p, sl.ptr, p->lh) : build_lists<double>(p, sl.ptr, p->lh);
+    if (rc) return rc;
+    sl.owner = p->uid;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return p->p.dtype == LAM_C64 ? run_fwd<float>(p, sl.ptr, u, false, nullptr, d, true, s)
+                               : run_fwd<double>(p, sl.ptr, u, false, nullptr, d, true, s);
 }
 
 int lam_profile(lam_plan p, int on) {

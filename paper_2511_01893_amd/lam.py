@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         for name in ("lam_fwd", "lam_adj", "lam_fwd_real", "lam_adj_real", "lam_adj_hat"):
             getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_fwd_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.lam_fwd_scratch.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_data_hat.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.lam_fwd_streamed.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p]
         L.lam_adj_streamed.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p]
@@ -102,7 +103,8 @@ class Plan:
 
     def __init__(self, n0: int, n1: int | None = None, n2: int | None = None, *, ntheta: int, phi: float,
                  h: int | None = None, w: int | None = None, m: int = 4, oversample: int = 2,
-                 dtype: torch.dtype = torch.complex64, slab: int = 0, theta=None, device="cuda"):
+                 dtype: torch.dtype = torch.complex64, slab: int = 0, theta=None, device="cuda",
+                 workspace: bool = True):
         n1 = n0 if n1 is None else n1
         n2 = n0 if n2 is None else n2
         h = n0 if h is None else h
@@ -121,10 +123,12 @@ class Plan:
             p.theta = ctypes.cast(self._theta, POINTER(c_double))
         self._h = c_void_p()
         _check(lib().lam_init(byref(self._h), byref(p)))
-        nbytes = lib().lam_workspace_bytes(self._h)
         self._home = torch.cuda.current_stream(self.device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        _check(lib().lam_set_workspace(self._h, c_void_p(self.workspace.data_ptr()), nbytes))
+        self.workspace = None
+        if workspace:   # workspace=False: a plan for fwd_scratch only (the library's static scratch)
+            nbytes = lib().lam_workspace_bytes(self._h)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _check(lib().lam_set_workspace(self._h, c_void_p(self.workspace.data_ptr()), nbytes))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -147,7 +151,8 @@ class Plan:
         while work of this call is pending on a stream other than the one they came from."""
         s = torch.cuda.current_stream(self.device)
         if s != self._home:
-            self.workspace.record_stream(s)
+            if self.workspace is not None:
+                self.workspace.record_stream(s)
             for t in tensors:
                 t.record_stream(s)
         return c_void_p(s.cuda_stream)
@@ -173,6 +178,15 @@ class Plan:
         self._arr(out, self.data_shape, "d")
         f = lib().lam_fwd if u.is_complex() else lib().lam_fwd_real
         _check(f(self._h, c_void_p(u.data_ptr()), c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def fwd_scratch(self, u: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """d = L u for complex u through lam_fwd_scratch: no workspace, nothing allocated (out is the
+        caller's); the plan's tables live in the library's static device scratch."""
+        self._arr(u, self.vol_shape, "u")
+        self._arr(out, self.data_shape, "d")
+        _check(lib().lam_fwd_scratch(self._h, c_void_p(u.data_ptr()), c_void_p(out.data_ptr()),
+                                     c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
         return out
 
     def adj(self, d: torch.Tensor, real: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:

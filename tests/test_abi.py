@@ -119,3 +119,18 @@ def test_no_device_reports_hip_error():
     assert lib.lam_set_workspace(h, c_void_p(0x100000), lib.lam_workspace_bytes(h)) == 3
     assert lib.lam_last_error().decode()
     lib.lam_destroy(h)
+
+
+def test_fwd_scratch_checks_size_before_the_device():
+    """lam_fwd_scratch refuses a plan larger than the static scratch (LAM_ERR_WORKSPACE) and null
+    arrays (LAM_ERR_ARG) before it touches a device."""
+    lib = L.lib()
+    for n, code in ((128, 4), (32, None)):
+        h = c_void_p()
+        assert lib.lam_init(byref(h), byref(_params(n0=n, n1=n, n2=n, h=n, w=n, ntheta=n))) == 0
+        assert lib.lam_fwd_scratch(h, None, None, None) == 1
+        if code is not None:
+            dummy = c_void_p(256)   # never dereferenced: the size check comes first
+            assert lib.lam_fwd_scratch(h, dummy, dummy, None) == code
+            assert b"scratch" in lib.lam_last_error()
+        lib.lam_destroy(h)
