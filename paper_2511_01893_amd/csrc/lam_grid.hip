@@ -12,13 +12,16 @@
 //   k_gather   stages a tile plus its (2m-1) halo in LDS and walks the tile's
 //              list, one lane per target: FP64 coordinates, weights, 2m x 2m
 //              FMA gather, optional fused "- d^" (Algorithm 2).
-//   k_scatter  accumulates one tile in LDS in FP64: its own list plus the
-//              border classes of the 8 neighbouring tiles whose stencils
-//              reach in, one lane per stencil column, one FP64 LDS atomic per
-//              stencil row (for m = 4 on large grids laid out so that each
-//              atomic instruction adds two adjacent rows of 4 targets, which
-//              spreads it evenly over the LDS banks).  Every cell of the tile
-//              is then written once.
+//   k_scatter_fx  (complex64, grids of at least 128 x 128, m <= 4) accumulates
+//              one tile in LDS in 64-bit fixed point, re and im packed in one
+//              integer per cell: its own list plus the border classes of the 8
+//              neighbouring tiles whose stencils reach in, one lane per stencil
+//              column, one integer LDS atomic per tap; bit-reproducible.
+//   k_scatter  the same in FP64 LDS atomics (complex128, and complex64 on
+//              smaller grids or for m > 4; for m = 4 on large grids laid out
+//              so that each atomic instruction adds two adjacent rows of 4
+//              targets, which spreads it evenly over the LDS banks).  Every
+//              cell of the tile is then written once.
 #include <type_traits>
 
 #include "lam_lists.hpp"
@@ -349,16 +352,17 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
 }
 
 // ---------------------------------------------------------------------------
-// F*_u2D spread into one tile of the oversampled grid.  Each lane adds its
-// column's 2m taps, one stencil row per FP64 LDS atomic (native ds_add_f64;
-// gfx950 runs FP64 LDS atomics ~20x faster than FP32 ones); a wave's 64 adds
-// cover NG targets' rows, GW adjacent cells each.
+// F*_u2D spread into one tile of the oversampled grid in FP64 (complex128; complex64 on grids
+// below 128 x 128 or for m > 4).  Each lane adds its column's 2m taps, one stencil row per FP64
+// LDS atomic (native ds_add_f64; gfx950 runs FP64 LDS atomics ~20x faster than FP32 ones); a
+// wave's 64 adds cover NG targets' rows, GW adjacent cells each.
 //
-// LTS > 0 fixes the tile size 2^LTS at compile time and requires M1, M2 >= 2^LTS + 16: stencil
-// rows and columns are then folded positions relative to the tile, so a row's cell is the row
-// base plus a constant (immediate LDS offsets) and the test for the tile is one compare.
+// LTS > 0 (with PAIRS, m = 4) fixes the tile size 2^LTS at compile time and requires M1, M2 >=
+// 2^LTS + 16: stencil rows and columns are then folded positions relative to the tile, so a row's
+// cell is the row base plus a constant (immediate LDS offsets) and the test for the tile is one
+// compare.
 //
-// PAIRS (m = 4 on the folded path) changes only how the adds are laid out.  An atomic
+// PAIRS changes how the adds are laid out.  An atomic
 // instruction whose 8-lane groups each add one row of a different target hits the banks at
 // random (~16 cycles per 64-lane FP64 add); one whose 16-lane rows each add two adjacent
 // rows of one target covers every bank equally (PA = 8 (mod 32) doubles puts the second row
@@ -371,7 +375,7 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
                                                  Dims D, Tables<T> tb, int log2TS_) {
   constexpr int W = 2 * MH, GW = group_width<MH>(), NG = 64 / GW;
   static_assert(LTS == 0 || W <= 16, "folded positions assume at most 16 taps");
-  static_assert(!PAIRS || (MH == 4 && LTS > 0), "row pairs: m = 4 on the folded path");
+  static_assert(PAIRS == (LTS > 0) && (!PAIRS || MH == 4), "the folded path is the row-pair path, m = 4");
   const int log2TS = LTS > 0 ? LTS : log2TS_;
   const int TS = 1 << log2TS, PA = TS + 8;   // PA = 8 (mod 32): stencil rows of a target fall in distinct banks
   const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
@@ -500,29 +504,15 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
           target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
           const double fy = floor(sy), fx = floor(sx);
           const int by = (int)fy, bx = (int)fx;
-          int col, r0;
-          if constexpr (LTS > 0) {
-            col = fold_rel(bx - MH + 1 - x0, M2) + j;
-            r0 = fold_rel(by - MH + 1 - y0, M1);
-          } else {
-            col = (bx - MH + 1 + j - x0) & (M2 - 1);
-            r0 = by - MH + 1 - y0;
-          }
+          const int col = (bx - MH + 1 + j - x0) & (M2 - 1), r0 = by - MH + 1 - y0;
           if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
             const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
             T wc, up, dn;
             fg.seeds((T)(sy - fy), wc, up, dn);
-            const int ab = r0 * PA + col;   // cell (r0, col); row iy adds iy * PA (folded path)
             auto add = [&](int iy, double x, double y) {
-              int a;
-              if constexpr (LTS > 0) {
-                if ((unsigned)(r0 + iy) >= (unsigned)TS) return;
-                a = ab + iy * PA;
-              } else {
-                const int row = (r0 + iy) & (M1 - 1);
-                if (row >= TS) return;
-                a = __umul24(row, PA) + col;
-              }
+              const int row = (r0 + iy) & (M1 - 1);
+              if (row >= TS) return;
+              const int a = __umul24(row, PA) + col;
               atomicAdd(are + a, x);
               atomicAdd(aim + a, y);
             };
@@ -569,6 +559,182 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   for (int e = tid; e < TS * TS; e += nth) {
     const int r = e >> log2TS, c = e & (TS - 1);
     G[(size_t)(y0 + r) * M2 + x0 + c] = mk((T)are[r * PA + c], (T)aim[r * PA + c]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F*_u2D spread of complex64 samples into one 64 x 64 tile (grids of at least 128 x 128, m <= 4)
+// in 64-bit fixed point.  Each cell accumulates re * 2^32 + im as one 64-bit integer, re and im
+// being the tap's contribution scaled by the tile's power-of-two scale S and rounded to 32-bit
+// integers: one integer LDS atomic (ds_add_u64) per tap instead of two FP64 ones, and integer sums
+// do not depend on the order of the adds, so the spread is bit-reproducible.  The low word of a sum
+// is exactly the sum of the im parts, the high word the sum of the re parts less one where the im
+// sum is negative, as long as both sums stay inside 32 bits; S keeps them below 2^30:
+//   pass 1  every target adds max(|re|, |im|) of its sample to the 8 x 8 block of the tile that
+//           holds its stencil base (clamped to the tile's edge blocks); a target's stencil reaches
+//           only the blocks next to its base block, and |weight| <= 1, so the 3 x 3 sum around a
+//           block bounds |re| and |im| of every cell of that block; S = 2^(30 - e) with 2^e above
+//           the largest such bound;
+//   pass 2  8 lanes per target, lane j adding stencil column j for all 2m rows (each target's
+//           coordinates evaluated by one lane of a quad and broadcast).  The accumulator
+//           carries a guard band of 2m - 1 cells on every side, so taps that leave the tile land in
+//           the guard (the neighbouring tile adds them) and no tap needs a bounds test.
+// A tile whose bound is not finite (NaN or Inf samples) is written as NaN.
+// ---------------------------------------------------------------------------
+// Value of lane U of the lane's quad (DPP quad_perm; every lane is written, so no old value).
+template <int U>
+__device__ __forceinline__ int quad_copy(int v) { return __builtin_amdgcn_mov_dpp(v, U * 0x55, 0xf, 0xf, false); }
+template <int U>
+__device__ __forceinline__ float quad_copy(float v) { return __int_as_float(quad_copy<U>(__float_as_int(v))); }
+
+// floor(a b + 1/2) as an integer: one FMA and one floor conversion (v_cvt_flr_i32_f32, which the
+// compiler does not form from floorf), i.e. a b rounded to the nearest integer.  Truncation would
+// bias every tap towards zero, and the bias of coherent taps adds up.
+__device__ __forceinline__ int round_to_int(float a, float b) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(__builtin_fmaf(a, b, 0.5f)));
+  return r;
+}
+
+template <int MH>
+constexpr int fx_pitch() { return 64 + 2 * (2 * MH - 1); }
+template <int MH>
+constexpr size_t fx_lds() { return (size_t)fx_pitch<MH>() * fx_pitch<MH>() * 8 + 64 * 8 + 16; }
+
+template <int MH>
+__global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict__ in, cpx<float>* __restrict__ Gb,
+                                                    int k0, Dims D, Tables<float> tb) {
+  constexpr int W = 2 * MH, GD = W - 1, PT = fx_pitch<MH>(), TS = 64, LTS = 6, GW = 8, NG = 64 / GW;
+  static_assert(W <= GW, "one lane per stencil column");
+  const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
+  const int ntx = M2 >> LTS, nty = M1 >> LTS;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(lam_smem);   // [PT][PT], cell (r, c) at (r + GD) PT + c + GD
+  double* blk = reinterpret_cast<double*>(acc + PT * PT);                       // [8][8] block sums
+  float* scal = reinterpret_cast<float*>(blk + 64);                             // S, 1 / S, finite flag
+  // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
+  const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
+  const int tix = tb.sperm[(size_t)k * ntx * nty + rank];
+  const int tx = tix % ntx, ty = tix / ntx;
+  const int x0 = tx * TS, y0 = ty * TS;
+  for (int e = tid; e < PT * PT; e += nth) acc[e] = 0ull;
+  for (int e = tid; e < 64; e += nth) blk[e] = 0.0;
+  int rb[kSpreadSlots], re[kSpreadSlots], pre[kSpreadSlots + 1];
+  spread_ranges(tb.toff + (size_t)k * ((size_t)ntx * nty * 9 + 1), ntx, nty, ty, tx, rb, re);
+  pre[0] = 0;
+#pragma unroll
+  for (int q = 0; q < kSpreadSlots; ++q) pre[q + 1] = pre[q] + (re[q] - rb[q]);
+  const int total = pre[kSpreadSlots];
+  // list index of position i of the tile's ranges (the last slot starting at or before i holds it)
+  auto idx_of = [&](int i) {
+    int idx = rb[0] + i;
+#pragma unroll
+    for (int q = 1; q < kSpreadSlots; ++q)
+      if (i >= pre[q]) idx = rb[q] + (i - pre[q]);
+    return idx;
+  };
+  const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
+  const unsigned hw = (unsigned)D.h * D.w;   // < 2^24
+  const int kw = k * D.w;
+  __syncthreads();
+  // pass 1: block sums of max(|re|, |im|) at the stencil bases
+  for (int i = tid; i < total; i += nth) {
+    const int pe = L[idx_of(i)];
+    const unsigned t = (unsigned)pe >> 12;
+    const int uk = pe & 4095;
+    const cpx<float> v = in[(size_t)t * hw + (unsigned)(kw + uk)];
+    double sx, sy;
+    target_coords(D.xy, tb.cth[t], tb.sth[t], k, uk, sx, sy);
+    const int bx = min(max(fold_rel((int)floor(sx) - x0, M2) >> 3, 0), 7);
+    const int by = min(max(fold_rel((int)floor(sy) - y0, M1) >> 3, 0), 7);
+    atomicAdd(blk + by * 8 + bx, (double)fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int bx = tid & 7, by = tid >> 3;
+    double b = 0.0;
+    for (int yy = max(by - 1, 0); yy <= min(by + 1, 7); ++yy)
+      for (int xx = max(bx - 1, 0); xx <= min(bx + 1, 7); ++xx) b += blk[yy * 8 + xx];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b = fmax(b, __shfl_xor(b, o));
+    if (tid == 0) {
+      int e = 0;
+      if (b > 0.0 && b <= 1e300) (void)frexp(b, &e);   // b < 2^e
+      const int sh = min(max(30 - e, -126), 126);
+      scal[0] = ldexpf(1.0f, sh);
+      scal[1] = ldexpf(1.0f, -sh);
+      scal[2] = (b <= 1e300) ? 1.0f : 0.0f;   // NaN fails the test too
+    }
+  }
+  __syncthreads();
+  const float S = scal[0];
+  // pass 2: the taps, over the tile's own list and then the neighbours' border classes.  A lane
+  // group of 8 takes U = 4 targets per wave step; lane j of the group evaluates target j & 3
+  // (FP64 coordinates, cell address, row weights, scaled sample; the group's two quads evaluate
+  // the same four), and a quad broadcast (DPP) hands each target's values to every lane in turn.
+  // The NG targets of one instruction come from NG far-apart stretches of the positions: the lists
+  // hold runs of neighbouring targets, whose stencils overlap, and adds to one cell within an
+  // instruction serialise.
+  constexpr int U = 4;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+  const int g = lane / GW, j = lane & (GW - 1), js = j & 3;
+  const Fgg<float> fg(D.beta);
+  auto spread = [&](int n, auto list_idx) {
+    const int stretch = (n + NG * U - 1) / (NG * U);
+    for (int i0 = wave; i0 < stretch; i0 += nwave) {
+      // this lane's target: the group's js-th
+      const int is = (js * NG + g) * stretch + i0;
+      const bool oks = is < n;
+      const int pe = oks ? L[list_idx(is)] : 0;
+      const unsigned ts = (unsigned)pe >> 12;
+      const int uks = pe & 4095;
+      const cpx<float> vs = in[(size_t)ts * hw + (unsigned)(kw + uks)];
+      double sx, sy;
+      target_coords(D.xy, tb.cth[ts], tb.sth[ts], k, uks, sx, sy);
+      const double fy = floor(sy), fx = floor(sx);
+      // address of the stencil's first cell, -1: no target
+      const int as = oks ? __umul24(fold_rel((int)fy - MH + 1 - y0, M1) + GD, PT) + fold_rel((int)fx - MH + 1 - x0, M2) + GD
+                         : -1;
+      const float dxs = (float)(sx - fx);
+      float wys[W];
+      fgg_taps<float, MH>(fg, (float)(sy - fy), wys);
+      const float vxs = vs.x * S, vys = vs.y * S;
+      auto target = [&](auto UC) {
+        constexpr int u = decltype(UC)::value;
+        const int a0 = quad_copy<u>(as);
+        const float dx = quad_copy<u>(dxs), vx = quad_copy<u>(vxs), vy = quad_copy<u>(vys);
+        float wy[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) wy[i] = quad_copy<u>(wys[i]);
+        if (a0 < 0 || j >= W) return;
+        const float wxj = fg.one(dx - (float)(j + 1 - MH));
+        const float pvx = wxj * vx, pvy = wxj * vy;
+        unsigned long long* a = acc + a0 + j;
+#pragma unroll
+        for (int iy = 0; iy < W; ++iy) {
+          const int xi = round_to_int(pvx, wy[iy]), yi = round_to_int(pvy, wy[iy]);
+          const unsigned long long pk = ((unsigned long long)(unsigned)(xi + (yi >> 31)) << 32) | (unsigned)yi;
+          atomicAdd(a + iy * PT, pk);
+        }
+      };
+      target(std::integral_constant<int, 0>());
+      target(std::integral_constant<int, 1>());
+      target(std::integral_constant<int, 2>());
+      target(std::integral_constant<int, 3>());
+    }
+  };
+  spread(pre[1], [&](int i) { return rb[0] + i; });
+  spread(total - pre[1], [&](int i) { return idx_of(i + pre[1]); });
+  __syncthreads();
+  const float iS = scal[1];
+  const bool finite = scal[2] != 0.0f;
+  cpx<float>* G = Gb + (size_t)kk * M1 * M2;
+  for (int e = tid; e < TS * TS; e += nth) {
+    const int r = e >> LTS, cc = e & (TS - 1);
+    const unsigned long long X = acc[(r + GD) * PT + cc + GD];
+    const int im = (int)(unsigned)X, rl = (int)(unsigned)(X >> 32) - (im >> 31);
+    G[(size_t)(y0 + r) * M2 + x0 + cc] =
+        finite ? mk((float)rl * iS, (float)im * iS) : mk(__builtin_nanf(""), __builtin_nanf(""));
   }
 }
 
@@ -649,12 +815,20 @@ template <typename T>
 hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int k0, int ns, const Dims& D,
                           const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
+  const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
   LAM_MH_SWITCH(D.m, {
+    if constexpr (std::is_same<T, float>::value && MH <= 4) {
+      if (fast_tiles(c, D)) {   // complex64: fixed-point accumulation
+        auto kf = k_scatter_fx<MH>;
+        if ((e = prep(kf, fx_lds<MH>())) != hipSuccess) return e;
+        hipLaunchKernelGGL(kf, dim3(ntiles * ns), dim3(512), fx_lds<MH>(), s, in, Gb, k0, D, tb);
+        return hipGetLastError();
+      }
+    }
     auto k = k_scatter<T, MH>;
     if constexpr (MH == 4)
       if (fast_tiles(c, D)) k = k_scatter<T, MH, 6, true>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
-    const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
     hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
   });
   return hipGetLastError();
