@@ -37,7 +37,10 @@ is the cited unequally-spaced FFT literature):
 * ``F*_2D`` is the centred inverse DFT with ``1/(h w)``; the adjoint's
   ``F_2D`` is the centred forward DFT with ``1/(h w)`` (the exact adjoint).
 
-LSP / ADMM-TV (Section 2, Algorithms 1 and 2) follow ``admm_step`` below.
+LSP / ADMM-TV (Section 2, Algorithms 1 and 2) follow ``admm_step`` below;
+``admm_step_memo`` takes the LSP's operator applications through private
+per-chunk memoization caches (Section 4.4, Equation (cs)), with a
+sign-random-projection key in place of the paper's CNN encoder.
 
 Every function here is pinned in ``tests/test_oracle_*.py`` against the
 exact nonuniform DFT, the closed-form projection of a Gaussian blob, the
@@ -400,6 +403,151 @@ def admm_step(u, psi, lam, rho, dhat, g: Geometry, alpha: float, n_inner: int):
     grad u + lambda/rho, lambda += rho (grad u - psi), and residual balancing
     with r = |grad u - psi| and s = rho |grad^T (psi - psi_prev)|."""
     u = lsp(u, psi, lam, rho, dhat, g, n_inner)
+    gu = grad3(u)
+    psi_prev = psi
+    psi = tv_shrink(gu + lam / rho, alpha / rho)
+    lam = lam + rho * (gu - psi)
+    r = np.linalg.norm(gu - psi)
+    s = rho * np.linalg.norm(grad3_adj(psi - psi_prev))
+    return u, psi, lam, penalty_update(rho, r, s)
+
+
+# --------------------------------------------------------------------------
+# memoization (Section 4.4 "Memoization Cache", Section 4.5 Equation (cs))
+# --------------------------------------------------------------------------
+SPLITMIX_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, counter: np.ndarray) -> np.ndarray:
+    """Output number ``counter`` (0, 1, ...) of Steele, Lea and Flood's SplitMix64
+    generator started from state ``seed``: the state advances by the golden-ratio
+    gamma before each output, which is then mixed by two xor-shift-multiply
+    rounds and a final xor-shift.  uint64 arithmetic wraps modulo 2^64."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(counter, dtype=np.uint64) + np.uint64(1)) * SPLITMIX_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def sketch(x: np.ndarray, key_dim: int, seed: int, op: int, chunk: int) -> np.ndarray:
+    """Key of one input chunk: a signed random projection (count sketch) standing in
+    for the paper's CNN encoder.  The chunk's values in C order, complex ones as
+    (re, im) pairs, are numbered q = 0, 1, ...; value q goes to bucket q mod key_dim
+    with sign +1 or -1 from the top bit of SplitMix64 output number
+    chunk * 2^40 + q of state seed + op.  Key = bucket sums (FP64)."""
+    v = np.asarray(x)
+    v = v.astype(np.complex128).view(np.float64).ravel() if np.iscomplexobj(v) else v.astype(np.float64).ravel()
+    q = np.arange(v.size, dtype=np.uint64)
+    z = splitmix64(seed + op, q + (np.uint64(chunk) << np.uint64(40)))
+    sign = 1.0 - 2.0 * (z >> np.uint64(63)).astype(np.float64)
+    return np.bincount((q % np.uint64(key_dim)).astype(np.int64), weights=sign * v, minlength=key_dim)
+
+
+def cosine(a: np.ndarray, b: np.ndarray) -> float:
+    """Cosine similarity of two keys (Equation (cs)); 0 when either is zero."""
+    na, nb = np.linalg.norm(a), np.linalg.norm(b)
+    return float(np.dot(a, b) / (na * nb)) if na > 0 and nb > 0 else 0.0
+
+
+class MemoOp:
+    """One operator with a private memoization cache per chunk location (Section 4.4):
+    one (key, value) item per chunk, replaced first-in-first-out.  A query whose key
+    has cosine similarity above ``tau`` with the chunk's cached key takes the cached
+    value; otherwise the operator's output for that chunk is computed and replaces
+    the item.  The input is chunked along axis ``ain`` and the output along ``aout``
+    in chunks of ``chunk`` (the last one may be shorter); ``fn(x, chunks)`` returns
+    the operator's output, exact at least on the listed chunks."""
+
+    def __init__(self, fn, ain: int, aout: int, chunk: int, tau: float, key_dim: int, seed: int, op: int):
+        self.fn, self.ain, self.aout, self.chunk = fn, ain, aout, chunk
+        self.tau, self.key_dim, self.seed, self.op = tau, key_dim, seed, op
+        self.keys, self.vals = {}, {}
+        self.hits = self.misses = 0
+
+    def _sl(self, axis: int, c: int, ndim: int):
+        s = [slice(None)] * ndim
+        s[axis] = slice(c * self.chunk, (c + 1) * self.chunk)
+        return tuple(s)
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        nch = -(-x.shape[self.ain] // self.chunk)
+        keys = [sketch(x[self._sl(self.ain, c, x.ndim)], self.key_dim, self.seed, self.op, c) for c in range(nch)]
+        hit = [c in self.keys and cosine(keys[c], self.keys[c]) > self.tau for c in range(nch)]
+        miss = [c for c in range(nch) if not hit[c]]
+        out = self.fn(x, miss) if miss else None
+        res = []
+        for c in range(nch):
+            if hit[c]:
+                self.hits += 1
+            else:
+                self.keys[c], self.vals[c] = keys[c], np.array(out[self._sl(self.aout, c, out.ndim)])
+                self.misses += 1
+            res.append(self.vals[c])
+        return np.concatenate(res, axis=self.aout)
+
+
+class Memo:
+    """The four memoized operators of the cancelled LSP (Algorithm 2): F_u1D and F*_u1D
+    chunked along the volume's y axis (they act on whole z columns), F_u2D and F*_u2D
+    along k_v (they act on whole slices)."""
+
+    def __init__(self, g: Geometry, tau: float, chunk_y: int, chunk_kv: int, key_dim: int, seed: int):
+        def u1(x, chunks):
+            return fu1d(x, g)
+
+        def u2(x, chunks):
+            return fu2d(x, g, kv_list=[k for c in chunks for k in range(c * chunk_kv, min((c + 1) * chunk_kv, g.h))])
+
+        def u2a(x, chunks):
+            return fu2d_adj(x, g, kv_list=[k for c in chunks for k in range(c * chunk_kv, min((c + 1) * chunk_kv, g.h))])
+
+        def u1a(x, chunks):
+            return fu1d_adj(x, g)
+
+        self.ops = [MemoOp(u1, 1, 1, chunk_y, tau, key_dim, seed, 0),     # F_u1D: u[z, y, x] -> u1[k_v, y, x]
+                    MemoOp(u2, 0, 1, chunk_kv, tau, key_dim, seed, 1),    # F_u2D: u1[k_v] -> u2[theta, k_v, k_u]
+                    MemoOp(u2a, 1, 0, chunk_kv, tau, key_dim, seed, 2),   # F*_u2D: r[theta, k_v] -> u1[k_v]
+                    MemoOp(u1a, 1, 1, chunk_y, tau, key_dim, seed, 3)]    # F*_u1D: u1[k_v, y, x] -> u[z, y, x]
+
+    def fwd_hat(self, u, dhat):
+        return self.ops[1](self.ops[0](u)) - dhat
+
+    def adj_hat(self, r):
+        return self.ops[3](self.ops[2](r))
+
+    def counts(self):
+        return [(op.hits, op.misses) for op in self.ops]
+
+
+def lsp_memo(u, psi, lam, rho, dhat, g: Geometry, n_inner: int, memo: Memo):
+    """``lsp`` with the forward pass and the adjoint pass of every inner iteration taken
+    through the memoized operators (Algorithm 2's shaded statements replaced by
+    memoization, Section 4); the exact line search applies the plain L^ to the
+    direction."""
+    hw = g.h * g.w
+    gg = psi - lam / rho
+    G_prev = None
+    p = None
+    for _ in range(n_inner):
+        r = memo.fwd_hat(u, dhat)
+        gp = grad3(u)
+        G = memo.adj_hat(r).real / hw + rho * grad3_adj(gp - gg)
+        if G_prev is None:
+            p = -G
+        else:
+            p = -G + (np.vdot(G, G).real / np.vdot(G_prev, G_prev).real) * p
+        Lp = lam_fwd_hat(p, g)
+        den = np.vdot(Lp, Lp).real / hw + rho * np.vdot(grad3(p), grad3(p)).real
+        gamma = -np.vdot(G, p).real / den
+        u = u + gamma * p
+        G_prev = G
+    return u
+
+
+def admm_step_memo(u, psi, lam, rho, dhat, g: Geometry, alpha: float, n_inner: int, memo: Memo):
+    """``admm_step`` with ``lsp_memo`` in place of ``lsp``."""
+    u = lsp_memo(u, psi, lam, rho, dhat, g, n_inner, memo)
     gu = grad3(u)
     psi_prev = psi
     psi = tv_shrink(gu + lam / rho, alpha / rho)
