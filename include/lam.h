@@ -210,6 +210,46 @@ int lam_admm_step(lam_plan p, const lam_admm_state* s, const void* dhat, int n_i
 #define LAM_SCRATCH_BYTES ((size_t)64 << 20)
 int lam_fwd_scratch(lam_plan p, const void* u, void* d, void* hip_stream);
 
+/* Memoization of the LSP's operator applications (Section 4.4 "Memoization Cache", Section 4.5
+ * Equation (cs)).  Each of F_u1D, F_u2D, F*_u2D and F*_u1D keeps a private cache per chunk location
+ * (chunk_y volume rows for the z steps, chunk_kv k_v slices for the 2D steps): one (key, value) item,
+ * replaced first-in-first-out.  The key of an input chunk is a signed random projection of length
+ * key_dim (count sketch: value q of the chunk, C order, complex values as (re, im), adds to bucket
+ * q mod key_dim with the sign of the top bit of SplitMix64 output number chunk * 2^40 + q from state
+ * seed + operator index 0..3), standing in for the paper's CNN encoder.  A query whose key has cosine
+ * similarity above tau with the chunk's cached key takes the cached output; otherwise the chunk is
+ * computed and its (key, output) replaces the item.
+ *   tau        similarity threshold; tau >= 1 never hits (the plain step), the paper uses 0.92
+ *   chunk_y    power of two in [1, n1]; chunk_kv power of two in [1, h]
+ *   key_dim    power of two in [64, 4096]
+ *   work       device memory of lam_memo_bytes bytes holding the caches (outputs of the four
+ *              operators), keys, flags and the sign tables; caller-owned, ZERO-FILLED before the
+ *              first step of a solve (empty caches); keep it across the steps of one solve
+ *   counters   device array of 8 int64: hits and misses of F_u1D, F_u2D, F*_u2D, F*_u1D, accumulated
+ *              by every step (the caller clears them) */
+typedef struct {
+  double tau;
+  int chunk_y;
+  int chunk_kv;
+  int key_dim;
+  unsigned long long seed;
+  void* work;
+  long long* counters;
+} lam_memo;
+
+/* Bytes of memoization work for the plan and the parameters in *m (0 for invalid parameters). */
+size_t lam_memo_bytes(lam_plan p, const lam_memo* m);
+
+/* lam_admm_step with memoized operators: every inner iteration recomputes the residual
+ * r = M_u2D(M_u1D u) - d^ and the data gradient Re M*_u1D(M*_u2D r) / (h w) through the memoized
+ * operators (Algorithm 2's forward and adjoint passes; F_u2D's cached outputs exclude d^, so dhat may
+ * change between steps), then takes the Fletcher-Reeves direction p and the exact line search, which
+ * applies the plain L^ to p.  RSP, multiplier and penalty updates as lam_admm_step.  With tau >= 1 it
+ * computes what lam_admm_step does (up to rounding: the residual is recomputed, not updated).  Enqueues
+ * work only.  Errors: as lam_admm_step; LAM_ERR_ARG for parameters outside the ranges above. */
+int lam_admm_step_memo(lam_plan p, const lam_admm_state* s, const void* dhat, int n_inner, const lam_memo* m,
+                       void* hip_stream);
+
 /* Per-kernel timing, for measurement.  With profiling on, every kernel the
  * plan launches is bracketed by a pair of HIP events recorded on its stream
  * (this adds a small gap between kernels).  lam_profile_read waits for the

@@ -17,6 +17,7 @@
 
 #include "lam_admm.hpp"
 #include "lam_internal.hpp"
+#include "lam_memo.hpp"
 
 namespace lam {
 namespace {
@@ -312,6 +313,59 @@ int step(lam_plan pl, const lam_admm_state* s, const void* dhat, int n_inner, hi
   return hip_ok(hipGetLastError());
 }
 
+// One ADMM-TV iteration with the LSP's forward and adjoint passes memoized (Section 4.4): every inner
+// iteration recomputes the residual r = M_u2D(M_u1D u) - d^ and the gradient
+// G = Re M*_u1D(M*_u2D r) / (h w) + rho grad^T(grad u - g) through the memoized operators (Algorithm 2's
+// forward and adjoint passes), then takes the Fletcher-Reeves direction p and the exact line search,
+// which applies the plain L^ to p.  The RSP, multiplier and penalty updates are those of step().
+template <typename T>
+int step_memo(lam_plan pl, const lam_admm_state* s, const void* dhat, int n_inner, const lam_memo& m, hipStream_t st) {
+  const lam_params& q = plan_params(pl);
+  const WorkLayout W = layout(q);
+  unsigned char* w = static_cast<unsigned char*>(s->work);
+  cpx<T>* r = reinterpret_cast<cpx<T>*>(w + W.r);
+  cpx<T>* Lp = reinterpret_cast<cpx<T>*>(w + W.lp);
+  T* G = reinterpret_cast<T*>(w + W.g);
+  T* p = reinterpret_cast<T*>(w + W.p);
+  T* D = reinterpret_cast<T*>(w + W.d);
+  double* part = reinterpret_cast<double*>(w + W.part);
+  double* sc = reinterpret_cast<double*>(w + W.sc);
+  T* u = static_cast<T*>(s->u);
+  T* psi = static_cast<T*>(s->psi);
+  T* mult = static_cast<T*>(s->lam);
+  double* user = s->scal;
+  void* U1 = plan_u1(pl);
+  Vol v{q.n0, q.n1, q.n2, (size_t)q.n0 * q.n1 * q.n2, (size_t)q.n1 * q.n2};
+  const size_t P = (size_t)q.ntheta * q.h * q.w;
+  const double inv_hw = 1.0 / ((double)q.h * (double)q.w);
+  const dim3 g(NB), b(NT);
+  int rc = memo_prepare(pl, m, st);
+  for (int it = 0; !rc && it < n_inner; ++it) {
+    rc = memo_apply<T>(pl, m, 0, u, U1, nullptr, st);                 // forward pass: F_u1D u
+    if (!rc) rc = memo_apply<T>(pl, m, 1, U1, r, dhat, st);           //   r = F_u2D u1 - d^
+    if (!rc) rc = memo_apply<T>(pl, m, 2, r, U1, nullptr, st);        // adjoint pass: F*_u2D r
+    if (!rc) rc = memo_apply<T>(pl, m, 3, U1, G, nullptr, st);        //   G = Re F*_u1D u1
+    if (rc) break;
+    hipLaunchKernelGGL(k_tv_grad<T>, g, b, 0, st, G, u, psi, mult, user, inv_hw, v, part);
+    hipLaunchKernelGGL(k_finish, dim3(1), b, 0, st, (int)F_GG, it == 0 ? 1 : 0, part, sc, user, inv_hw);
+    hipLaunchKernelGGL(k_cg_dir<T>, g, b, 0, st, G, p, sc, v.V, part);
+    hipLaunchKernelGGL(k_finish, dim3(1), b, 0, st, (int)F_GP, 0, part, sc, user, inv_hw);
+    if ((rc = hip_ok(hipGetLastError()))) break;
+    rc = plan_fwd_hat_real(pl, p, nullptr, Lp, st);                  // L^ p (exact line search)
+    if (rc) break;
+    hipLaunchKernelGGL(k_norm2_c<T>, g, b, 0, st, Lp, P, part);
+    hipLaunchKernelGGL(k_gradnorm<T>, g, b, 0, st, p, v, part + NB);
+    hipLaunchKernelGGL(k_finish, dim3(1), b, 0, st, (int)F_GAMMA, 0, part, sc, user, inv_hw);
+    hipLaunchKernelGGL(k_cg_update<T>, g, b, 0, st, u, p, r, Lp, sc, v.V, (size_t)0);   // u += gamma p
+    rc = hip_ok(hipGetLastError());
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rsp<T>, g, b, 0, st, u, psi, mult, D, user, v, part);
+  hipLaunchKernelGGL(k_divnorm<T>, g, b, 0, st, D, v, part + NB);
+  hipLaunchKernelGGL(k_finish, dim3(1), b, 0, st, (int)F_RHO, 0, part, sc, user, inv_hw);
+  return hip_ok(hipGetLastError());
+}
+
 }  // namespace
 }  // namespace lam
 
@@ -324,4 +378,16 @@ extern "C" int lam_admm_step(lam_plan p, const lam_admm_state* s, const void* dh
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   return lam::plan_params(p).dtype == LAM_C64 ? lam::step<float>(p, s, dhat, n_inner, st)
                                                 : lam::step<double>(p, s, dhat, n_inner, st);
+}
+
+extern "C" int lam_admm_step_memo(lam_plan p, const lam_admm_state* s, const void* dhat, int n_inner,
+                                  const lam_memo* m, void* stream) {
+  if (!p || !s || !dhat) return lam::set_error(LAM_ERR_ARG, "null argument");
+  if (!s->u || !s->psi || !s->lam || !s->work || !s->scal) return lam::set_error(LAM_ERR_ARG, "null state pointer");
+  if (n_inner < 1 || n_inner > 1000) return lam::set_error(LAM_ERR_ARG, "n_inner must be in [1, 1000]");
+  int rc = lam::memo_check(p, m, true);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  return lam::plan_params(p).dtype == LAM_C64 ? lam::step_memo<float>(p, s, dhat, n_inner, *m, st)
+                                                : lam::step_memo<double>(p, s, dhat, n_inner, *m, st);
 }

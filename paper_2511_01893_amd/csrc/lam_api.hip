@@ -553,6 +553,43 @@ int run_adj(lam_plan_s* P, const void* in, bool from_space, void* u, bool real_o
   return rc;
 }
 
+// One stage of L^ / L^* with the chunks whose hit flag is set skipped (memoized LSP): 0 F_u1D of a real
+// volume into the u1 buffer; 1 F_u2D of u1 into out (no subtraction); 2 F*_u2D of in into u1; 3 F*_u1D of
+// u1 into a real volume.  Chunks of 2^log2chunk volume rows (stages 0, 3) or k_v slices (1, 2).
+template <typename T>
+int run_stage(lam_plan_s* P, int stage, const void* in, void* out, const int* hit, int log2chunk, hipStream_t s) {
+  const Tables<T> tb = tables<T>(P);
+  const LaunchCfg& c = P->cfg;
+  Dims D = P->D;
+  D.skip = SkipMap{hit, log2chunk, 0};
+  cpx<T>* U1 = reinterpret_cast<cpx<T>*>(P->ws + P->off_u1);
+  cpx<T>* Tb = reinterpret_cast<cpx<T>*>(P->ws + P->off_t);
+  cpx<T>* Gb = reinterpret_cast<cpx<T>*>(P->ws + P->off_g);
+  const size_t zs = (size_t)P->p.n1 * P->p.n2;
+  if (stage == 0)
+    return timed(P, K_ZFWD, s, "F_u1D", [&] { return launch_zfwd<T>(c, in, true, U1, 0, P->p.n1, zs, D, tb, s); });
+  if (stage == 3)
+    return timed(P, K_ZADJ, s, "F*_u1D", [&] { return launch_zadj<T>(c, U1, out, true, 0, P->p.n1, zs, D, tb, s); });
+  int rc = 0;
+  for (int k0 = 0; !rc && k0 < P->p.h; k0 += P->slab) {
+    const int ns = std::min(P->slab, P->p.h - k0);
+    D.skip.off = k0;
+    if (stage == 1) {
+      cpx<T>* o = reinterpret_cast<cpx<T>*>(out);
+      rc = timed(P, K_YCOL_FWD, s, "F_u2D y-FFT", [&] { return launch_ycol_fwd<T>(c, U1, Tb, k0, ns, D, tb, s); });
+      if (!rc) rc = timed(P, K_XROW_FWD, s, "F_u2D x-FFT", [&] { return launch_xrow_fwd<T>(c, Tb, Gb, ns, D, tb, s); });
+      if (!rc)
+        rc = timed(P, K_GATHER, s, "F_u2D gather", [&] { return launch_gather<T>(c, Gb, o, nullptr, k0, ns, D, tb, s); });
+    } else {
+      const cpx<T>* r = reinterpret_cast<const cpx<T>*>(in);
+      rc = timed(P, K_SCATTER, s, "F*_u2D scatter", [&] { return launch_scatter<T>(c, r, Gb, k0, ns, D, tb, s); });
+      if (!rc) rc = timed(P, K_XROW_ADJ, s, "F*_u2D x-FFT", [&] { return launch_xrow_adj<T>(c, Gb, Tb, ns, D, tb, s); });
+      if (!rc) rc = timed(P, K_YCOL_ADJ, s, "F*_u2D y-FFT", [&] { return launch_ycol_adj<T>(c, Tb, U1, k0, ns, D, tb, s); });
+    }
+  }
+  return rc;
+}
+
 // d^ = W d: centred forward 2D DFT per projection, unnormalised (Algorithm 2's d^)
 template <typename T>
 int run_data_hat(lam_plan_s* P, const void* d, void* dhat, hipStream_t s) {
@@ -733,6 +770,11 @@ int plan_fwd_hat_real(lam_plan p, const void* u, const void* dhat, void* r, hipS
 }
 int plan_adj_hat_real(lam_plan p, const void* r, void* u, hipStream_t s) { return adj_any(p, r, false, u, true, s); }
 int set_error(int code, const char* msg) { return fail(code, msg); }
+void* plan_u1(lam_plan p) { return p->ws + p->off_u1; }
+int plan_stage(lam_plan p, int stage, const void* in, void* out, const int* hit, int log2chunk, hipStream_t s) {
+  return p->p.dtype == LAM_C64 ? run_stage<float>(p, stage, in, out, hit, log2chunk, s)
+                               : run_stage<double>(p, stage, in, out, hit, log2chunk, s);
+}
 }  // namespace lam
 
 // ---------------------------------------------------------------- static scratch

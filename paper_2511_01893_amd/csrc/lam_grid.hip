@@ -276,6 +276,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
   cpx<T>* tile = reinterpret_cast<cpx<T>*>(lam_smem);
   // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
   const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
+  if (D.skip.skip(kk)) return;
   const int tix = tb.gperm[(size_t)k * ntx * nty + rank];
   const int tx = tix % ntx, ty = tix / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
@@ -385,6 +386,7 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   double* aim = are + TS * PA;                                  // [TS][PA]
   // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
   const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
+  if (D.skip.skip(kk)) return;
   const int tix = tb.sperm[(size_t)k * ntx * nty + rank];
   const int tx = tix % ntx, ty = tix / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
@@ -614,6 +616,7 @@ __global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict
   float* scal = reinterpret_cast<float*>(blk + 64);                             // S, 1 / S, finite flag
   // blocks run rank-major over the slab's slices: the heaviest tile of every slice first
   const int ns = gridDim.x / (ntx * nty), rank = blockIdx.x / ns, kk = blockIdx.x - rank * ns, k = k0 + kk;
+  if (D.skip.skip(kk)) return;
   const int tix = tb.sperm[(size_t)k * ntx * nty + rank];
   const int tx = tix % ntx, ty = tix / ntx;
   const int x0 = tx * TS, y0 = ty * TS;

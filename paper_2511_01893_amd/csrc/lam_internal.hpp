@@ -6,12 +6,22 @@
 
 namespace lam {
 
+// Chunks whose memoized output is taken from the cache: a kernel whose unit (volume row y of the z
+// steps, slab-local k_v slice of the 2D steps) lies in chunk ((unit + off) >> log2chunk) with a
+// nonzero hit flag returns at once.  hit = nullptr: nothing is skipped.
+struct SkipMap {
+  const int* hit;
+  int log2chunk, off;
+  __device__ __forceinline__ bool skip(int unit) const { return hit && hit[(unit + off) >> log2chunk]; }
+};
+
 // Sizes passed by value to every kernel.
 struct Dims {
   int n0, n1, n2, h, w, ntheta, m;
   int log2M0, log2M1, log2M2;
   double beta;      // Gaussian exponent in grid units, pi (R - 1/2) / (R m)
   XYGeom xy;
+  SkipMap skip;     // memoized chunks (lam_admm_step_memo); empty otherwise
 };
 
 // Device tables (inside the caller's workspace), built in FP64 on the host.

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // blockIdx.y is the row within the input slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
+  if (D.skip.skip(y)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const size_t plane = (size_t)D.n1 * D.n2;
   const cpx<T> zero = mk((T)0, (T)0);
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
   const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // blockIdx.y is the row within the output slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
+  if (D.skip.skip(y)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const size_t plane = (size_t)D.n1 * D.n2;
   // per-row stencil bases and offsets and the inverse runs, after the buffer
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
   const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
   const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
+  if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
   for (int e = tid; e < (M1 - n1) * TX; e += nth) buf[(n1 / 2) * TX + e] = zero;
@@ -241,6 +244,7 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
   const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
   const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
+  if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> v[vpt<T>()];
@@ -272,6 +276,7 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
   const int log2RB = LN > 0 ? LB : log2RB_, log2M2 = LN > 0 ? LN : D.log2M2;
   const int RB = 1 << log2RB, M2 = 1 << log2M2, n2 = M2 / 2, log2n2 = log2M2 - 1;
   const size_t r0 = (size_t)blockIdx.x * RB;
+  if (D.skip.skip((int)(r0 >> D.log2M1))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
   // R = 2: the padded positions of each row are [n2/2, M2 - n2/2), n2 of them
@@ -306,6 +311,7 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
   const int log2RB = LN > 0 ? LB : log2RB_, log2M2 = LN > 0 ? LN : D.log2M2;
   const int RB = 1 << log2RB, M2 = 1 << log2M2, n2 = M2 / 2, log2n2 = log2M2 - 1;
   const size_t r0 = (size_t)blockIdx.x * RB;
+  if (D.skip.skip((int)(r0 >> D.log2M1))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> v[vpt<T>()];

@@ -54,6 +54,11 @@ class AdmmState(ctypes.Structure):
                 ("scal", POINTER(c_double))]
 
 
+class LamMemo(ctypes.Structure):
+    _fields_ = [("tau", c_double), ("chunk_y", c_int), ("chunk_kv", c_int), ("key_dim", c_int),
+                ("seed", ctypes.c_ulonglong), ("work", c_void_p), ("counters", POINTER(ctypes.c_longlong))]
+
+
 _lib = None
 
 
@@ -79,6 +84,9 @@ def lib() -> ctypes.CDLL:
         L.lam_admm_work_bytes.argtypes = [c_void_p]
         L.lam_admm_work_bytes.restype = c_size_t
         L.lam_admm_step.argtypes = [c_void_p, POINTER(AdmmState), c_void_p, c_int, c_void_p]
+        L.lam_memo_bytes.argtypes = [c_void_p, POINTER(LamMemo)]
+        L.lam_memo_bytes.restype = c_size_t
+        L.lam_admm_step_memo.argtypes = [c_void_p, POINTER(AdmmState), c_void_p, c_int, POINTER(LamMemo), c_void_p]
         L.lam_profile.argtypes = [c_void_p, c_int]
         L.lam_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(ctypes.c_longlong)]
         L.lam_kernel_name.argtypes = [c_int]
@@ -304,15 +312,49 @@ class LamOp(torch.autograd.Function):
         return ctx.plan.adj(g.contiguous(), real=ctx.real), None
 
 
+OPS = ("F_u1D", "F_u2D", "F*_u2D", "F*_u1D")
+
+
+class Memo:
+    """Private per-chunk memoization caches of the LSP's four operators for one ADMM solve
+    (Section 4.4): chunks of chunk_y volume rows (F_u1D, F*_u1D) and chunk_kv k_v slices (F_u2D,
+    F*_u2D), sketch keys of length key_dim, similarity threshold tau (Equation (cs)).  The device
+    work (caches, keys, sign tables) starts zeroed, i.e. with empty caches."""
+
+    def __init__(self, plan: Plan, tau: float = 0.92, chunk_y: int = 16, chunk_kv: int = 16,
+                 key_dim: int = 1024, seed: int = 0):
+        self.params = LamMemo(float(tau), int(chunk_y), int(chunk_kv), int(key_dim), int(seed), None, None)
+        nbytes = lib().lam_memo_bytes(plan._h, byref(self.params))
+        if nbytes == 0:
+            raise ValueError("memoization parameters: chunk_y, chunk_kv powers of two within the volume rows / "
+                             "detector rows, key_dim a power of two in [64, 4096], tau not NaN")
+        self.tau = float(tau)
+        self.work = torch.zeros(nbytes, dtype=torch.uint8, device=plan.device)
+        self.counters = torch.zeros(8, dtype=torch.int64, device=plan.device)
+        self.params.work = c_void_p(self.work.data_ptr())
+        self.params.counters = ctypes.cast(c_void_p(self.counters.data_ptr()), POINTER(ctypes.c_longlong))
+
+    def stats(self) -> dict:
+        """{operator: (hits, misses)} accumulated over the steps so far (synchronises)."""
+        c = self.counters.tolist()
+        return {name: (c[2 * i], c[2 * i + 1]) for i, name in enumerate(OPS)}
+
+    def hit_rate(self) -> float:
+        c = self.counters.tolist()
+        return sum(c[0::2]) / max(1, sum(c))
+
+
 class AdmmTV:
     """ADMM-TV state on the device for min_u 1/2 |L u - d|^2 + alpha |u|_TV (Equation 1).
 
     u (real), psi and lam (3 x volume) start at zero; rho starts at rho0.
     step() runs one ADMM iteration (LSP with n_inner CG steps, RSP, multiplier
-    and penalty updates) entirely in liblam.so's kernels."""
+    and penalty updates) entirely in liblam.so's kernels; with a Memo, the
+    LSP's operator applications go through its caches (lam_admm_step_memo)."""
 
-    def __init__(self, plan: Plan, alpha: float, rho0: float = 0.5):
+    def __init__(self, plan: Plan, alpha: float, rho0: float = 0.5, memo: Memo | None = None):
         self.plan = plan
+        self.memo = memo
         dev, rdt = plan.device, plan.rdtype
         self.u = torch.zeros(plan.vol_shape, dtype=rdt, device=dev)
         self.psi = torch.zeros((3,) + plan.vol_shape, dtype=rdt, device=dev)
@@ -336,8 +378,13 @@ class AdmmTV:
         st = AdmmState(c_void_p(self.u.data_ptr()), c_void_p(self.psi.data_ptr()), c_void_p(self.lam.data_ptr()),
                        c_void_p(self.work.data_ptr()),
                        ctypes.cast(c_void_p(self.scal.data_ptr()), POINTER(c_double)))
-        _check(lib().lam_admm_step(self.plan._h, byref(st), c_void_p(dhat.data_ptr()), n_inner,
-                                   self.plan._stream(self.work)))
+        if self.memo is None:
+            _check(lib().lam_admm_step(self.plan._h, byref(st), c_void_p(dhat.data_ptr()), n_inner,
+                                       self.plan._stream(self.work)))
+        else:
+            _check(lib().lam_admm_step_memo(self.plan._h, byref(st), c_void_p(dhat.data_ptr()), n_inner,
+                                            byref(self.memo.params),
+                                            self.plan._stream(self.work, self.memo.work, self.memo.counters)))
 
 
 def admm_tv(plan: Plan, d: torch.Tensor, alpha: float, n_outer: int = 4, n_inner: int = 4,

@@ -134,3 +134,26 @@ def test_fwd_scratch_checks_size_before_the_device():
             assert lib.lam_fwd_scratch(h, dummy, dummy, None) == code
             assert b"scratch" in lib.lam_last_error()
         lib.lam_destroy(h)
+
+
+def test_memo_parameters_and_layout():
+    """lam_memo: struct layout as in lam.h; lam_memo_bytes is 0 for parameters outside the
+    documented ranges and covers the four operators' outputs otherwise; lam_admm_step_memo
+    refuses bad arguments before touching a device."""
+    assert ctypes.sizeof(L.LamMemo) == 48 and L.LamMemo.seed.offset == 24 and L.LamMemo.counters.offset == 40
+    lib = L.lib()
+    h = c_void_p()
+    assert lib.lam_init(byref(h), byref(_params())) == 0
+    m = L.LamMemo(0.92, 8, 8, 256, 0, None, None)
+    n = lib.lam_memo_bytes(h, byref(m))
+    V, H1, P = 32 ** 3, 32 ** 3, 32 ** 3
+    assert n >= 4 * (V + 2 * H1 + 2 * P + 2 * H1 + V) // 4        # the caches (complex64 outputs)
+    for bad in (dict(chunk_y=3), dict(chunk_y=64), dict(chunk_kv=0), dict(key_dim=32), dict(key_dim=8192),
+                dict(key_dim=1000), dict(tau=float("nan"))):
+        mb = L.LamMemo(0.92, 8, 8, 256, 0, None, None)
+        for k, v in bad.items():
+            setattr(mb, k, v)
+        assert lib.lam_memo_bytes(h, byref(mb)) == 0, bad
+    st = L.AdmmState(None, None, None, None, None)
+    assert lib.lam_admm_step_memo(h, byref(st), c_void_p(256), 4, byref(m), None) == 1
+    lib.lam_destroy(h)
