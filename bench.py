@@ -10,6 +10,10 @@ Prints one JSON line.  Besides the contract fields it reports:
   roofline       dominant kernel's algorithmic rate against its bound,
                  from per-kernel HIP events in a second pass of the same steps
   pair_hbm_frac  the whole pair's algorithmic bytes (u, u1, u2, d traffic) / time / 8 TB/s
+                 (also with the oversampled grid's traffic, and for the frequency-domain pair)
+  alu            flops of the pair (FFTs 5 N log2 N, 5 per stencil tap) against the FP32 peaks
+  memo           memoized ADMM-TV (private per-chunk caches): accuracy and hit rate against tau,
+                 time per step
   fp64_*         the same kernels instantiated in complex128 (the plain FP64 operator)
   accuracy       c64 vs c128 GPU (whole arrays) and c64 vs the FP64 oracle on sampled slices
   cpu_baseline   the FP64 oracle timed on a bounded sample on this host
@@ -39,6 +43,19 @@ def algorithmic_bytes(n0, n1, n2, ntheta, h, w, s, su):
     """Bytes one operator must move (u read, u1 written + read, u2 written + read, d written)."""
     V, H1, P = n0 * n1 * n2, h * n1 * n2, ntheta * h * w
     return su * V + 2 * s * H1 + 3 * s * P
+
+
+def pair_flops(n0, n1, n2, ntheta, h, w, m=4):
+    """Flops of one pair: 5 N log2 N per FFT of length N (padded lengths, no pruning), 5 per
+    stencil tap of the gathers and spreads; each operator: z FFTs of 2 n0 on n1 n2 columns and h x 2m
+    taps per column, y FFTs of 2 n1 on n2 columns and x FFTs of 2 n2 on 2 n1 rows per slice,
+    (2m)^2 taps per target, and the h x w 2D DFT of every projection."""
+    def fft(N):
+        return 5.0 * N * math.log2(N)
+    op = (n1 * n2 * (fft(2 * n0) + 5.0 * h * 2 * m)
+          + h * (n2 * fft(2 * n1) + 2 * n1 * fft(2 * n2)) + 5.0 * ntheta * h * w * (2 * m) ** 2
+          + ntheta * (h * fft(w) + w * fft(h)))
+    return 2.0 * op
 
 
 def kernel_units(name, plan, s, su, slab):
@@ -122,6 +139,58 @@ def cpu_baseline(wl, budget_slices=16, col_fraction=16, nproj=32):
     }
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs this process may use, and RAM of the host."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = 0
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpus": len(os.sched_getaffinity(0)), "ram_gb": round(ram / 1e9, 1)}
+
+
+def oracle_pair_c2(reps=3):
+    """One full FP64 oracle pair (L u, L* d) at the 256^3 workload, timed reps times (median): the
+    oracle as it stands, F_u2D slices split over the host's threads (the tests' harness)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import lam_oracle as O
+    from paper_2511_01893_amd import inputs as I
+
+    w = I.WORKLOADS["lam256"]
+    n = w["n"]
+    g = O.Geometry(n, n, n, w["ntheta"], math.radians(w["phi_deg"]), w["det"], w["det"], 2, 4)
+    u = I.blob_phantom(g.vol_shape, I.draw_blobs(w["seed"], w["nblobs"]))
+    d = I.random_detector_data(g.data_shape, w["seed"])
+    nw = len(os.sched_getaffinity(0))
+    sets = [list(range(i, g.h, nw)) for i in range(nw)]
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        u1 = O.fu1d(u, g)
+        with ThreadPoolExecutor(nw) as ex:
+            u2 = sum(ex.map(lambda ks: O.fu2d(u1, g, kv_list=ks), sets))
+        O.f2d_inv(u2)
+        r = O.f2d(d)
+        with ThreadPoolExecutor(nw) as ex:
+            a1 = sum(ex.map(lambda ks: O.fu2d_adj(r, g, kv_list=ks), sets))
+        O.fu1d_adj(a1, g)
+        times.append(time.perf_counter() - t)
+    return {"seconds_per_pair": float(np.median(times)), "runs": times, "workload": "lam256", "threads": nw}
+
+
 def sampled_oracle_check(plan, u_host, kv_list):
     """c64 GPU L^ u vs the FP64 oracle on a few k_v slices (full F_u1D on the host)."""
     import numpy as np
@@ -134,6 +203,52 @@ def sampled_oracle_check(plan, u_host, kv_list):
     ref = O.fu2d(u1, g, kv_list=kv_list)[:, kv_list, :]
     got = plan.fwd_hat(torch.from_numpy(u_host).to(plan.dtype).cuda())[:, kv_list, :].cpu().numpy()
     return O.relerr(got.astype(np.complex128), ref)
+
+
+def memo_study(lam, I, dev, wl_name="lam256", n_outer=20, n_inner=4,
+               taus=(0.86, 0.88, 0.90, 0.92, 0.94, 0.96, 0.99, 0.999, 0.9999)):
+    """Memoized ADMM-TV (Section 4.4) against the plain one on a synthetic workload: the plain
+    device step gives R_comp, the memoized step at each tau gives R_LB; accuracy = 1 - |R_comp -
+    R_LB|_F / |R_comp|_F (the evaluation section's metric), hit rates of the four operators' private
+    caches (chunks of 16 rows / slices, sketch keys of 1024), and the time per ADMM step with the
+    caches, without any hit (tau = 2: the same recomputing LSP) and for the plain step."""
+    import torch
+
+    wl = I.WORKLOADS[wl_name]
+    n, nt, h = wl["n"], wl["ntheta"], wl["det"]
+    phi = math.radians(wl["phi_deg"])
+    plan = lam.Plan(n, ntheta=nt, phi=phi, h=h, w=h, dtype=torch.complex64, device=dev)
+    u_true = I.blob_phantom_torch((n, n, n), I.draw_blobs(wl["seed"], wl["nblobs"], cube_layer=wl["cubes"], n=n),
+                                  dev, torch.float32)
+    dre = plan.fwd(u_true).real
+    noise = torch.from_numpy(I.gaussian_noise(tuple(dre.shape), wl["seed"], 0.01 * dre.abs().max().item())).to(dev)
+    dhat = plan.data_hat(torch.complex(dre + noise.float(), torch.zeros_like(dre)))
+    del dre, noise, u_true
+
+    def run(tau):
+        memo = None if tau is None else lam.Memo(plan, tau=tau, chunk_y=16, chunk_kv=16, key_dim=1024, seed=1)
+        s = lam.AdmmTV(plan, 1e-3, rho0=0.5, memo=memo)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n_outer):
+            s.step(dhat, n_inner)
+        e1.record()
+        torch.cuda.synchronize()
+        return s, memo, e0.elapsed_time(e1) / n_outer
+
+    ref, _, ms_plain = run(None)
+    _, m2, ms_nohit = run(2.0)
+    rows = []
+    for tau in taus:
+        s, m, ms = run(tau)
+        acc = 1.0 - ((s.u - ref.u).norm() / ref.u.norm()).item()
+        rows.append({"tau": tau, "accuracy": acc, "hit_rate": m.hit_rate(), "ms_per_step": ms,
+                     "hits_misses": m.stats()})
+        log(f"[bench] memo tau {tau}: accuracy {acc:.4f}, hit rate {m.hit_rate():.3f}, {ms:.2f} ms per step")
+    return {"workload": f"{wl_name} (tilt {wl['phi_deg']:g} deg) phantom + 1 % noise, alpha 1e-3, "
+                        f"{n_outer} outer x {n_inner} inner, chunks of 16, sketch keys of 1024",
+            "ms_per_step_plain": ms_plain, "ms_per_step_no_hits": ms_nohit, "table": rows}
 
 
 def source_digest() -> str:
@@ -171,6 +286,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle accuracy check")
     ap.add_argument("--slab", type=int, default=0, help="k_v slices per 2D-step slab (0: automatic)")
+    ap.add_argument("--no-memo", action="store_true", help="skip the memoized ADMM-TV study")
+    ap.add_argument("--oracle-c2", action="store_true",
+                    help="also time three full FP64 oracle pairs at 256^3 (several minutes of host time)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -231,6 +349,30 @@ def main():
             "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dom, plan_slab),
             "bytes_per_launch": bytes_launch, "avg_launch_ms": kern[dom]["avg_launch_ms"]}
 
+    # the frequency-domain pair that the CG loop runs (Algorithm 2): L^ u - d^ and L^* r
+    r = torch.empty_like(d)
+    uh = torch.empty_like(u)
+    for _ in range(args.warmup):
+        plan.fwd_hat(u, d, out=r)
+        plan.adj_hat(r, out=uh)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.fwd_hat(u, d, out=r)
+        plan.adj_hat(r, out=uh)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_hat = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] frequency-domain pair (L^, L^*) {ms_hat:.3f} ms")
+    del r, uh
+    flops = pair_flops(n, n, n, nt, h, h)
+    G_bytes = 2 * 2 * (4 * n * n * h * 8)          # per operator the oversampled grid written and read
+    alu = {"flops_per_pair": flops, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+           "frac_fp32_78.6": flops / (ms * 1e-3) / (FP32_VALU_TFLOPS * 1e12),
+           "frac_fp32_157.3": flops / (ms * 1e-3) / (157.3e12),
+           "note": "78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz, packed FP32 disabled; 157.3 with packing"}
+
     result = {
         "metric": "lam fwd+adj pairs/s at 512^3 (c64 vs FP64, rel err <=1e-4); % HBM roofline",
         "value": 1000.0 / ms,
@@ -250,6 +392,11 @@ def main():
                    "slab": plan_slab},
         "pair_algorithmic_bytes": B_pair,
         "pair_hbm_frac": B_pair / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "pair_hbm_frac_with_grid": (B_pair + G_bytes) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "hat_pair_ms": ms_hat,
+        # L^ u - d^: u read, u1 written and read, d^ read, r written; L^* r: r read, u1 written and read, u written
+        "hat_pair_hbm_frac": (B_pair - 3 * 8 * nt * h * h) / (ms_hat * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "alu": alu,
         "roofline": roof,
         "kernels": kern,
     }
@@ -276,10 +423,22 @@ def main():
         result["accuracy"]["oracle_sample"] = f"L^ u on k_v slices {kvs} (all angles, all k_u)"
         log(f"[bench] c64 vs oracle (slices {kvs}) {err:.2e} in {time.perf_counter() - t:.1f} s")
 
+    if not args.no_memo:
+        t = time.perf_counter()
+        result["memo"] = memo_study(lam, I, dev)
+        log(f"[bench] memo study in {time.perf_counter() - t:.1f} s")
+        torch.cuda.empty_cache()
+
     if not args.no_cpu:
         t = time.perf_counter()
         result["cpu_baseline"] = cpu_baseline(wl)
+        result["cpu_baseline"].update(host_info())
         log(f"[bench] cpu baseline {result['cpu_baseline']['value']:.3e} pairs/s in {time.perf_counter() - t:.1f} s")
+
+    if args.oracle_c2:
+        t = time.perf_counter()
+        result["oracle_pair_lam256"] = oracle_pair_c2()
+        log(f"[bench] oracle 256^3 pair {result['oracle_pair_lam256']['seconds_per_pair']:.1f} s (median of 3)")
 
     print(json.dumps(result), flush=True)
 
