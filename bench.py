@@ -14,6 +14,7 @@ Prints one JSON line.  Besides the contract fields it reports:
   alu            flops of the pair (FFTs 5 N log2 N, 5 per stencil tap) against the FP32 peaks
   memo           memoized ADMM-TV (private per-chunk caches): accuracy and hit rate against tau,
                  time per step
+  offload        ADMM-Offload plan for one ADMM-TV iteration (profiled phases, host link bandwidth)
   fp64_*         the same kernels instantiated in complex128 (the plain FP64 operator)
   accuracy       c64 vs c128 GPU (whole arrays) and c64 vs the FP64 oracle on sampled slices
   cpu_baseline   the FP64 oracle timed on a bounded sample on this host
@@ -251,6 +252,76 @@ def memo_study(lam, I, dev, wl_name="lam256", n_outer=20, n_inner=4,
             "ms_per_step_plain": ms_plain, "ms_per_step_no_hits": ms_nohit, "table": rows}
 
 
+def offload_study(lam, I, dev, wl_name="lam512", n_inner=4):
+    """ADMM-Offload planning (Section 5.1) for one ADMM-TV iteration of the given workload on this
+    GPU: phase durations from timings of the device step (t(n) = a + n b for n inner iterations,
+    L^ timed alone, the remainder split between the RSP with the multiplier update and the penalty
+    update by their bytes), the host link's bandwidth from pinned 1 GiB copies each way, and the
+    ADMM variables of the paper's formulation with their accesses: g = psi - lambda/rho formed at the
+    LSP's start and read through it, psi and lambda read there and updated in the RSP, D = psi -
+    psi_prev written in the RSP and read by the penalty update, the CG work written and used in the
+    LSP; u stays resident.  Reports the planner's choice, and M and T of the paper's choice
+    (psi, lambda, g), with and without a memory budget of half the variables."""
+    import torch
+
+    wl = I.WORKLOADS[wl_name]
+    n, nt, h = wl["n"], wl["ntheta"], wl["det"]
+    plan = lam.Plan(n, ntheta=nt, phi=math.radians(wl["phi_deg"]), h=h, w=h, dtype=torch.complex64, device=dev)
+    d = I.random_complex_torch(plan.data_shape, wl["seed"] + 200, dev, torch.complex64)
+    dhat = plan.data_hat(d)
+    u0 = torch.zeros(plan.vol_shape, dtype=torch.complex64, device=dev)
+    r = torch.empty_like(d)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    s = lam.AdmmTV(plan, 1e-3, rho0=0.5)
+    t1 = timed(lambda: s.step(dhat, 1))
+    tn = timed(lambda: s.step(dhat, n_inner))
+    b = (tn - t1) / (n_inner - 1)
+    a = t1 - b
+    t_fwd = timed(lambda: plan.fwd_hat(u0, dhat, out=r))
+    V = n * n * n
+    rest = max(a - t_fwd, 1e-6)
+    t_rsp, t_pen = rest * 16.0 / 19.0, rest * 3.0 / 19.0          # bytes: RSP 16 V floats, penalty 3 V
+    t_lsp = t_fwd + n_inner * b
+    t_g = 9.0 * V * 4 / 4.5e12                                      # forming g: read psi, lambda, write g
+    host = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+    devb = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    h2d = timed(lambda: devb.copy_(host, non_blocking=True))
+    d2h = timed(lambda: host.copy_(devb, non_blocking=True))
+    link = (1 << 30) / max(h2d, d2h)
+    del host, devb
+    f4 = 4.0 * V
+    P = nt * h * h
+    variables = {
+        "psi": {"bytes": 3 * f4, "access": {0: (0.0, t_g, False), 1: (0.0, t_rsp, False)}},
+        "lambda": {"bytes": 3 * f4, "access": {0: (0.0, t_g, False), 1: (0.0, t_rsp, False)}},
+        "g": {"bytes": 3 * f4, "access": {0: (0.0, t_lsp, True)}},
+        "D": {"bytes": 3 * f4, "access": {1: (0.0, t_rsp, True), 2: (0.0, t_pen, False)}},
+        "cg_work": {"bytes": 2 * f4 + 4 * 4.0 * P, "access": {0: (0.0, t_lsp, True)}},
+    }
+    phases = [t_lsp, t_rsp, t_pen]
+    resident = f4                                                    # u
+    total = resident + sum(v["bytes"] for v in variables.values())
+    out = {"workload": f"{wl_name}, complex64, {n_inner} inner", "phase_s": phases, "link_GBps": link / 1e9,
+           "bytes_total": total, "plan": lam.offload_plan(phases, variables, resident, link),
+           "paper_choice": lam.offload_evaluate(phases, variables, resident, link, ["psi", "lambda", "g"]),
+           "plan_budget_half": lam.offload_plan(phases, variables, resident, link, budget=0.5 * total)}
+    log(f"[bench] offload: phases {[round(x * 1e3, 2) for x in phases]} ms, link {link / 1e9:.1f} GB/s; plan "
+        f"{out['plan']['offload']} M {out['plan']['M'] / 1e9:.2f} GB T {out['plan']['T'] * 1e3:.2f} ms; "
+        f"psi/lambda/g: M {out['paper_choice']['M'] / 1e9:.2f} GB T {out['paper_choice']['T'] * 1e3:.2f} ms")
+    return out
+
+
 def source_digest() -> str:
     """SHA-256 over the HIP sources: counter-derived figures are valid only for the kernels they were taken on."""
     import hashlib
@@ -287,6 +358,7 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle accuracy check")
     ap.add_argument("--slab", type=int, default=0, help="k_v slices per 2D-step slab (0: automatic)")
     ap.add_argument("--no-memo", action="store_true", help="skip the memoized ADMM-TV study")
+    ap.add_argument("--no-offload", action="store_true", help="skip the ADMM-Offload planning study")
     ap.add_argument("--oracle-c2", action="store_true",
                     help="also time three full FP64 oracle pairs at 256^3 (several minutes of host time)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -427,6 +499,12 @@ def main():
         t = time.perf_counter()
         result["memo"] = memo_study(lam, I, dev)
         log(f"[bench] memo study in {time.perf_counter() - t:.1f} s")
+        torch.cuda.empty_cache()
+
+    if not args.no_offload:
+        t = time.perf_counter()
+        result["offload"] = offload_study(lam, I, dev, args.workload)
+        log(f"[bench] offload study in {time.perf_counter() - t:.1f} s")
         torch.cuda.empty_cache()
 
     if not args.no_cpu:

@@ -250,6 +250,50 @@ size_t lam_memo_bytes(lam_plan p, const lam_memo* m);
 int lam_admm_step_memo(lam_plan p, const lam_admm_state* s, const void* dhat, int n_inner, const lam_memo* m,
                        void* hip_stream);
 
+/* ADMM-Offload planning (Section 5.1).  One ADMM iteration is nphases phases run back to back and
+ * repeated (phase_s: durations in seconds, e.g. LSP, RSP, multiplier update, penalty update, from a
+ * profile of one iteration).  Each variable has a size, whether it is an offloading candidate, and
+ * per phase whether the phase accesses it, the offsets (seconds from the phase's start) of its first
+ * and last access there, and whether the phase overwrites it before reading it (its old value is then
+ * dead before the phase).  The planner evaluates every set of candidates: after each access phase k,
+ * up to the variable's next access phase k', a dead gap leaves it absent with no transfer; otherwise
+ * it is offloaded after its last access in k unless the offload cannot end before its first access in
+ * k' (the maximum prefetch distance, constraint 3), and prefetched after the offload (constraint 1),
+ * as late as lets it end when k' starts (constraint 4), unless no prefetch distance is left
+ * (constraint 2).  One link of link_bps bytes/s carries one transfer at a time: offloads in the order
+ * of their last accesses, then prefetches in the order of their planned starts.  M = the bytes of
+ * all variables less the plan's peak of resident bytes over the iteration; T = the sum of the delays
+ * of prefetches that end after the first access they serve; MT = M / max(T, 1 us).  The plan with
+ * the largest MT wins (the empty plan has M = 0, MT = 0; ties keep the plan whose candidate bitmask is
+ * smaller).  With budget > 0 only plans whose peak (resident + variables - M) fits the budget
+ * compete; if none does, out->MT = -1.  Host computation only; no device is touched.
+ * Errors: LAM_ERR_ARG for null pointers, counts outside [1, 8] phases / [1, 16] variables, durations
+ * not positive, offsets outside [0, duration] or first > last, a variable with no access. */
+#define LAM_OFFLOAD_MAX_PHASES 8
+#define LAM_OFFLOAD_MAX_VARS 16
+typedef struct {
+  double bytes;
+  int candidate;
+  int accessed[LAM_OFFLOAD_MAX_PHASES];
+  double first[LAM_OFFLOAD_MAX_PHASES];
+  double last[LAM_OFFLOAD_MAX_PHASES];
+  int writes_first[LAM_OFFLOAD_MAX_PHASES];
+} lam_offload_var;
+typedef struct {
+  unsigned mask;   /* bit v set: variable v is offloaded */
+  double M;        /* memory saving, bytes */
+  double T;        /* performance loss, seconds per iteration */
+  double MT;       /* M / max(T, 1e-6), or -1 when no plan fits the budget */
+  double peak;     /* resident + variables - M, bytes */
+} lam_offload_result;
+int lam_offload_plan(const double* phase_s, int nphases, const lam_offload_var* vars, int nvars, double resident,
+                     double link_bps, double budget, lam_offload_result* out);
+
+/* M, T, MT and peak of one plan (bit v of mask: variable v offloaded, candidate or not), by the rules
+ * of lam_offload_plan.  Errors as lam_offload_plan; LAM_ERR_ARG for mask bits at or beyond nvars. */
+int lam_offload_evaluate(const double* phase_s, int nphases, const lam_offload_var* vars, int nvars, double resident,
+                         double link_bps, unsigned mask, lam_offload_result* out);
+
 /* Per-kernel timing, for measurement.  With profiling on, every kernel the
  * plan launches is bracketed by a pair of HIP events recorded on its stream
  * (this adds a small gap between kernels).  lam_profile_read waits for the

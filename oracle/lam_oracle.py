@@ -557,6 +557,136 @@ def admm_step_memo(u, psi, lam, rho, dhat, g: Geometry, alpha: float, n_inner: i
     return u, psi, lam, penalty_update(rho, r, s)
 
 
+# --------------------------------------------------------------------------
+# ADMM-Offload planning (Section 5.1)
+# --------------------------------------------------------------------------
+def offload_plan(phase_s, sizes, access, resident, link_bps, candidates=None, budget=None):
+    """Choose the offloading/prefetch plan with the largest MT = M x 1/T (Section 5.1).
+
+    One ADMM iteration is the phases ``phase_s`` (seconds) run back to back and
+    repeated.  Variable v has ``sizes[v]`` bytes and, per phase k it is accessed in,
+    ``access[v][k] = (first, last, writes_first)``: offsets (seconds) of its first and
+    last access within the phase, and whether that phase overwrites it before reading
+    it (its old value is then dead before the phase).  ``resident`` bytes are never
+    offloaded; one copy link of ``link_bps`` bytes/s carries one transfer at a time.
+    Without a plan every variable stays in device memory.  A plan is a set of
+    variables; for each of them and each phase k accessing it, with k' the next phase
+    accessing it (cyclically, k itself one iteration on), the gap runs from its last
+    access in k (time L) to its first access in k' (time F); k' starts at S:
+      * a dead gap (k' writes first) needs no transfer: the variable is absent from L
+        to S;
+      * otherwise, taking the gaps in the order of L, the offload (size / link_bps)
+        starts at L or when the link is free; the gap is dropped unless the offload
+        ends before F (constraint 3: it fits the maximum prefetch distance F - L;
+        constraint 2: a prefetch distance is left);
+      * each kept gap's prefetch is planned after its offload (constraint 1), as late as
+        lets it end at S (constraint 4); taken in the order of their planned starts, each
+        goes into the first free stretch of the link at or after its planned start; the
+        variable is absent from its offload's end to its prefetch's start, and a prefetch
+        that ends after F delays the iteration by the difference (T sums the delays).
+    The transfers of one iteration are laid out on one unrolled timeline.  M is the total
+    of all sizes less the plan's peak of the resident sizes over the iteration (absences
+    folded onto one period).  MT = M / max(T, 1 microsecond), so plans without delay rank
+    by M.  Candidate plans are all subsets of ``candidates`` (default: every variable),
+    smallest bitmask first; the first plan with the largest MT wins (the empty plan has
+    M = 0 and MT = 0).  With a device-memory ``budget`` (bytes) only plans whose peak plus
+    ``resident`` fits it compete (the empty plan too); if none fits, the result names no
+    variables and has MT = -1.  Returns (chosen variables, M, T, MT, absences) with
+    absences = [(var, from, to)] of the chosen plan on the unrolled timeline."""
+    names = list(sizes) if candidates is None else list(candidates)
+    total = float(sum(sizes.values()))
+    fits = lambda M: budget is None or resident + total - M <= budget
+    best = (frozenset(), 0.0, 0.0, 0.0, []) if fits(0.0) else (frozenset(), 0.0, 0.0, -1.0, [])
+    for mask in range(1, 1 << len(names)):
+        plan = [names[j] for j in range(len(names)) if mask >> j & 1]
+        M, T, absent = offload_evaluate(plan, phase_s, sizes, access, link_bps)
+        MT = M / max(T, 1e-6)
+        if fits(M) and MT > best[3]:
+            best = (frozenset(plan), M, T, MT, absent)
+    return best
+
+
+def offload_evaluate(plan, phase_s, sizes, access, link_bps):
+    """(M, T, absences) of one plan, by the rules of ``offload_plan``."""
+    P = len(phase_s)
+    start = [0.0]
+    for t in phase_s:
+        start.append(start[-1] + t)
+    Ttot = start[P]
+
+    def gaps_of(v):
+        ks = sorted(access[v])
+        out = []
+        for i, k in enumerate(ks):
+            kn = ks[(i + 1) % len(ks)]
+            shift = Ttot if kn <= k else 0.0
+            L = start[k] + access[v][k][1]
+            F = start[kn] + access[v][kn][0] + shift
+            S = start[kn] + shift
+            out.append((L, F, S, bool(access[v][kn][2])))
+        return out
+
+    def first_fit(busy, ready, dur):
+        """Start of the first free stretch of length dur at or after ready."""
+        t = ready
+        for b, e in busy:
+            if t + dur <= b:
+                break
+            if t < e:
+                t = e
+        return t
+
+    def evaluate(plan):
+        gaps = [(g, v) for v in plan for g in gaps_of(v)]
+        absent, live = [], []
+        for (L, F, S, dead), v in gaps:
+            if dead:
+                absent.append((v, L, S))
+            else:
+                live.append((L, F, S, v))
+        busy, kept = [], []
+        free = 0.0
+        for L, F, S, v in sorted(live, key=lambda x: x[0]):
+            dur = sizes[v] / link_bps
+            b = max(L, free)
+            e = b + dur
+            if not e < F:                                       # constraints 2 and 3
+                continue
+            free = e
+            busy.append((b, e))
+            kept.append((max(e, S - dur), e, F, v))             # constraints 1 and 4
+        busy.sort()
+        delay = 0.0
+        for ps, oe, F, v in sorted(kept, key=lambda x: x[0]):
+            dur = sizes[v] / link_bps
+            b = first_fit(busy, ps, dur)
+            busy.append((b, b + dur))
+            busy.sort()
+            delay += max(0.0, b + dur - F)
+            absent.append((v, oe, b))
+        ev = []
+        for v, a, z in absent:                                  # absences folded onto [0, Ttot)
+            if z - a >= Ttot:
+                ev += [(0.0, -sizes[v]), (Ttot, sizes[v])]
+                continue
+            a0, z0 = a % Ttot, z % Ttot
+            if z0 >= a0:
+                ev += [(a0, -sizes[v]), (z0, sizes[v])]
+            else:
+                ev += [(a0, -sizes[v]), (Ttot, sizes[v]), (0.0, -sizes[v]), (z0, sizes[v])]
+        total = float(sum(sizes.values()))
+        ev.sort(key=lambda x: (x[0], x[1]))
+        cur, peak, i = total, None, 0
+        for t in sorted({0.0} | {t for t, _ in ev if t < Ttot}):   # resident just after each event time
+            while i < len(ev) and ev[i][0] <= t:
+                cur += ev[i][1]
+                i += 1
+            peak = cur if peak is None else max(peak, cur)
+        return total - peak, delay, absent
+
+    return evaluate(plan)
+
+
 def relerr(x: np.ndarray, ref: np.ndarray) -> float:
     """|x - ref|_2 / |ref|_2 (the relative Frobenius error of the evaluation section)."""
     return float(np.linalg.norm((np.asarray(x) - ref).ravel()) / np.linalg.norm(np.asarray(ref).ravel()))

@@ -20,7 +20,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblam.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["lam_api.hip", "lam_kernels.hip", "lam_grid.hip", "lam_admm.hip", "lam_memo.hip"]
+SOURCES = ["lam_api.hip", "lam_kernels.hip", "lam_grid.hip", "lam_admm.hip", "lam_memo.hip", "lam_offload.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

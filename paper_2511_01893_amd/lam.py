@@ -59,6 +59,15 @@ class LamMemo(ctypes.Structure):
                 ("seed", ctypes.c_ulonglong), ("work", c_void_p), ("counters", POINTER(ctypes.c_longlong))]
 
 
+class OffloadVar(ctypes.Structure):
+    _fields_ = [("bytes", c_double), ("candidate", c_int), ("accessed", c_int * 8), ("first", c_double * 8),
+                ("last", c_double * 8), ("writes_first", c_int * 8)]
+
+
+class OffloadResult(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_uint), ("M", c_double), ("T", c_double), ("MT", c_double), ("peak", c_double)]
+
+
 _lib = None
 
 
@@ -87,6 +96,10 @@ def lib() -> ctypes.CDLL:
         L.lam_memo_bytes.argtypes = [c_void_p, POINTER(LamMemo)]
         L.lam_memo_bytes.restype = c_size_t
         L.lam_admm_step_memo.argtypes = [c_void_p, POINTER(AdmmState), c_void_p, c_int, POINTER(LamMemo), c_void_p]
+        L.lam_offload_plan.argtypes = [POINTER(c_double), c_int, POINTER(OffloadVar), c_int, c_double, c_double,
+                                       c_double, POINTER(OffloadResult)]
+        L.lam_offload_evaluate.argtypes = [POINTER(c_double), c_int, POINTER(OffloadVar), c_int, c_double, c_double,
+                                           ctypes.c_uint, POINTER(OffloadResult)]
         L.lam_profile.argtypes = [c_void_p, c_int]
         L.lam_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(ctypes.c_longlong)]
         L.lam_kernel_name.argtypes = [c_int]
@@ -395,6 +408,44 @@ def admm_tv(plan: Plan, d: torch.Tensor, alpha: float, n_outer: int = 4, n_inner
     for _ in range(n_outer):
         s.step(dhat, n_inner)
     return s
+
+
+def _offload_args(phase_s, variables):
+    names = list(variables)
+    arr = (OffloadVar * len(names))()
+    for i, n in enumerate(names):
+        v = variables[n]
+        arr[i].bytes = float(v["bytes"])
+        arr[i].candidate = 1 if v.get("candidate", True) else 0
+        for k, (first, last, wf) in v["access"].items():
+            arr[i].accessed[k] = 1
+            arr[i].first[k] = float(first)
+            arr[i].last[k] = float(last)
+            arr[i].writes_first[k] = 1 if wf else 0
+    ph = (c_double * len(phase_s))(*[float(t) for t in phase_s])
+    return names, arr, ph
+
+
+def offload_plan(phase_s, variables: dict, resident: float, link_bps: float, budget: float | None = None) -> dict:
+    """ADMM-Offload plan (Section 5.1) by lam_offload_plan: phase durations (s), variables
+    {name: {"bytes", "access": {phase: (first, last, writes_first)}, "candidate"}}, never-offloaded
+    bytes, link bandwidth (bytes/s), optional device-memory budget (bytes)."""
+    names, arr, ph = _offload_args(phase_s, variables)
+    out = OffloadResult()
+    _check(lib().lam_offload_plan(ph, len(phase_s), arr, len(names), float(resident), float(link_bps),
+                                  float(budget) if budget else 0.0, byref(out)))
+    return {"offload": [n for i, n in enumerate(names) if out.mask >> i & 1], "M": out.M, "T": out.T, "MT": out.MT,
+            "peak": out.peak}
+
+
+def offload_evaluate(phase_s, variables: dict, resident: float, link_bps: float, offload) -> dict:
+    """M, T, MT and peak of the plan that offloads the named variables (lam_offload_evaluate)."""
+    names, arr, ph = _offload_args(phase_s, variables)
+    mask = sum(1 << names.index(n) for n in offload)
+    out = OffloadResult()
+    _check(lib().lam_offload_evaluate(ph, len(phase_s), arr, len(names), float(resident), float(link_bps), mask,
+                                      byref(out)))
+    return {"M": out.M, "T": out.T, "MT": out.MT, "peak": out.peak}
 
 
 def plan_for(name: str, dtype=torch.complex64, device="cuda", slab: int = 0) -> Plan:
