@@ -72,13 +72,14 @@ typedef enum {
 /* Problem statement (Section 2: volume n0 x n1 x n2, ntheta projection
  * angles, detector h x w; plus tilt, oversampling and kernel half-width). */
 typedef struct {
-  int n0, n1, n2;        /* volume (z, y, x); powers of two, 16 .. 4096            */
+  int n0, n1, n2;        /* volume (z, y, x); each 2^k or 3 2^k, 16 .. 4096 (the
+                            transforms of 3 2^k points take a radix-3 stage)        */
   int ntheta;            /* number of projection angles, 1 .. 4096                  */
   const double* theta;   /* host array [ntheta] in radians, or NULL: 2 pi t/ntheta  */
   double phi;            /* tilt of the rotation axis from the tomographic
                             position, radians, 0 <= phi < pi/2 (phi = 0: tomography) */
-  int h, w;              /* detector rows (k_v) and columns (k_u); powers of two,
-                            16 .. 4096                                              */
+  int h, w;              /* detector rows (k_v) and columns (k_u); each 2^k or
+                            3 2^k, 16 .. 4096                                       */
   int oversample;        /* R; must be 2                                            */
   int m;                 /* Gaussian half-width, 1 .. 8 (2m taps per axis)          */
   lam_dtype dtype;       /* LAM_C64: complex64 data, FP32 arithmetic, FP64
@@ -220,7 +221,8 @@ int lam_fwd_scratch(lam_plan p, const void* u, void* d, void* hip_stream);
  * similarity above tau with the chunk's cached key takes the cached output; otherwise the chunk is
  * computed and its (key, output) replaces the item.
  *   tau        similarity threshold; tau >= 1 never hits (the plain step), the paper uses 0.92
- *   chunk_y    power of two in [1, n1]; chunk_kv power of two in [1, h]
+ *   chunk_y    power of two in [1, n1]; chunk_kv power of two in [1, h]; the plan's n0, n1, n2, h
+ *              and w must be powers of two (LAM_ERR_ARG otherwise)
  *   key_dim    power of two in [64, 4096]
  *   work       device memory of lam_memo_bytes bytes holding the caches (outputs of the four
  *              operators), keys, flags and the sign tables; caller-owned, ZERO-FILLED before the

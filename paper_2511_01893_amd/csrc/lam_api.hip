@@ -32,7 +32,9 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-bool is_pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+// a transform length the kernels support: 2^k or 3 2^k, in [lo, hi]
+bool is_len_in(int v, int lo, int hi) { return v >= lo && v <= hi && (is_pow2(v) || (v % 3 == 0 && is_pow2(v / 3))); }
 int ilog2(long v) { int r = 0; while ((1L << r) < v) ++r; return r; }
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
@@ -52,11 +54,11 @@ struct lam_plan_s {
   lam_params p{};
   unsigned long long uid = 0;  // unique per plan (lam_init), names the owner of a device's scratch
   std::vector<double> theta;
-  int M0 = 0, M1 = 0, M2 = 0, Ntw = 0, slab = 0;
+  int M0 = 0, M1 = 0, M2 = 0, Ntw = 0, Ntw3 = 0, slab = 0;
   double beta = 0;
   size_t csize = 8, rsize = 4;
   // host tables (FP64)
-  std::vector<double> tw, cz, cy, cx, zdelta, cth, sth, rc, line;
+  std::vector<double> tw, tw3, cz, cy, cx, zdelta, cth, sth, rc, line;
   std::vector<int> zbase;
   std::vector<unsigned> zrun;
   // the tables as the device holds them (type per dtype), at their workspace offsets
@@ -64,7 +66,7 @@ struct lam_plan_s {
   // list-build buffers kept for plans that fit the static scratch (their rebuilds allocate nothing)
   ListHost lh;
   // workspace layout (byte offsets)
-  size_t off_tw = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zdelta = 0, off_cth = 0, off_sth = 0,
+  size_t off_tw = 0, off_tw3 = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zdelta = 0, off_cth = 0, off_sth = 0,
          off_rc = 0, off_line = 0, off_zrun = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -107,18 +109,24 @@ std::vector<double> deconv(int n, int R, int m) {
   return c;
 }
 
-void col_cfg(int log2N, int ncols, size_t csize, int& log2TX, int& threads, size_t& lds) {
-  const long N = 1L << log2N;
+// work-group size of an LDS FFT over N points x B transforms: N B / VPT values per thread and stage
+// (rounded up to whole waves for lengths 3 2^k), at least one wave
+int fft_threads(long N, long B, size_t csize) {
+  const long vp = vpt_of(csize);
+  return (int)std::max<long>(64, (N * B + vp * 64 - 1) / (vp * 64) * 64);
+}
+
+// column blocks of TX transforms of length N (TX a power of two dividing ncols)
+void col_cfg(long N, int ncols, size_t csize, int& log2TX, int& threads, size_t& lds) {
   int TX = 16;
   const int vp = vpt_of(csize);
-  while (TX > 1 && (TX > ncols || N * TX * (long)csize > 131072 || N * TX / vp > 1024)) TX >>= 1;
+  while (TX > 1 && (TX > ncols || ncols % TX || N * TX * (long)csize > 131072 || N * TX / vp > 1024)) TX >>= 1;
   log2TX = ilog2(TX);
-  threads = (int)std::max<long>(64, N * TX / vp);
+  threads = fft_threads(N, TX, csize);
   lds = (size_t)N * TX * csize;
 }
 
-void row_cfg(int log2N, long nrows, size_t csize, int& log2RB, int& threads, size_t& lds) {
-  const long N = 1L << log2N;
+void row_cfg(long N, long nrows, size_t csize, int& log2RB, int& threads, size_t& lds) {
   int RB = 16;
   // rows are contiguous in memory, so small row blocks stay coalesced: cap LDS at 32 KB so that
   // several work-groups share a CU and one's loads overlap another's FFT (the row kernels are
@@ -126,7 +134,7 @@ void row_cfg(int log2N, long nrows, size_t csize, int& log2RB, int& threads, siz
   const int vp = vpt_of(csize);
   while (RB > 1 && (RB > nrows || N * RB * (long)csize > 32768 || N * RB / vp > 1024 || nrows % RB)) RB >>= 1;
   log2RB = ilog2(RB);
-  threads = (int)std::max<long>(64, N * RB / vp);
+  threads = fft_threads(N, RB, csize);
   lds = (size_t)N * RB * csize * 9 / 8;     // one pad slot per 8 elements (bank spreading)
 }
 
@@ -145,14 +153,24 @@ int build(lam_plan_s* P) {
   P->rsize = P->csize / 2;
   P->M0 = R * p.n0; P->M1 = R * p.n1; P->M2 = R * p.n2;
   P->beta = M_PI * (R - 0.5) / (R * (double)m);
-  P->Ntw = std::max({P->M0, P->M1, P->M2, p.h, p.w});
-  // twiddles exp(-2 pi i t / Ntw) in FP64
-  P->tw.resize(2 * (size_t)P->Ntw);
-  for (int t = 0; t < P->Ntw; ++t) {
-    const double a = 2.0 * M_PI * (double)t / (double)P->Ntw;
-    P->tw[2 * t] = std::cos(a);
-    P->tw[2 * t + 1] = -std::sin(a);
+  // twiddles exp(-2 pi i t / Ntw) in FP64: one table for the power-of-two transform lengths (Ntw the
+  // largest of them, at least 8) and one for the lengths 3 2^k (Ntw3 the largest, 0: none)
+  P->Ntw = 8;
+  P->Ntw3 = 0;
+  for (int N : {P->M0, P->M1, P->M2, p.h, p.w}) {
+    if (is_pow2(N)) P->Ntw = std::max(P->Ntw, N);
+    else P->Ntw3 = std::max(P->Ntw3, N);
   }
+  auto twiddles = [](int n, std::vector<double>& tw) {
+    tw.resize(2 * (size_t)n);
+    for (int t = 0; t < n; ++t) {
+      const double a = 2.0 * M_PI * (double)t / (double)n;
+      tw[2 * (size_t)t] = std::cos(a);
+      tw[2 * (size_t)t + 1] = -std::sin(a);
+    }
+  };
+  twiddles(P->Ntw, P->tw);
+  twiddles(P->Ntw3, P->tw3);
   P->cz = deconv(p.n0, R, m);
   P->cy = deconv(p.n1, R, m);
   P->cx = deconv(p.n2, R, m);
@@ -173,7 +191,7 @@ int build(lam_plan_s* P) {
   {
     std::vector<std::vector<int>> rows(P->M0);
     for (int av = 0; av < p.h; ++av)
-      for (int i = 0; i < 2 * m; ++i) rows[(P->zbase[av] - m + 1 + i) & (P->M0 - 1)].push_back(av);
+      for (int i = 0; i < 2 * m; ++i) rows[(P->zbase[av] - m + 1 + i + 2 * P->M0) % P->M0].push_back(av);
     P->zrun.assign(2 * (size_t)P->M0, 0u);
     for (int q = 0; q < P->M0; ++q) {
       std::vector<int>& r = rows[q];
@@ -223,6 +241,7 @@ int build(lam_plan_s* P) {
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
   P->off_tw = take((size_t)P->Ntw * P->csize);
+  P->off_tw3 = take((size_t)P->Ntw3 * P->csize);
   P->off_cz = take((size_t)p.n0 * P->rsize);
   P->off_cy = take((size_t)p.n1 * P->rsize);
   P->off_cx = take((size_t)p.n2 * P->rsize);
@@ -233,8 +252,10 @@ int build(lam_plan_s* P) {
   P->off_rc = take(16 * sizeof(double));
   P->off_line = take(6 * (size_t)p.ntheta * sizeof(double));
   P->off_zrun = take(2 * (size_t)P->M0 * sizeof(unsigned));
-  // per-slice target lists of the tiles (built on the device by lam_set_workspace)
-  const int TS = std::min(64, std::min(P->M1, P->M2));
+  // per-slice target lists of the tiles (built on the device by lam_set_workspace); tiles of TS x TS,
+  // TS the largest power of two up to 64 that divides both grid periods
+  int TS = 64;
+  while (P->M1 % TS || P->M2 % TS) TS >>= 1;
   P->ntx = P->M2 / TS;
   P->nty = P->M1 / TS;
   P->off_tlist = take((size_t)p.h * p.ntheta * p.w * sizeof(int));
@@ -267,6 +288,7 @@ int build(lam_plan_s* P) {
     };
     P->blobs.clear();
     P->blobs.emplace_back(P->off_tw, real(P->tw));
+    if (P->Ntw3) P->blobs.emplace_back(P->off_tw3, real(P->tw3));
     P->blobs.emplace_back(P->off_cz, real(P->cz));
     P->blobs.emplace_back(P->off_cy, real(P->cy));
     P->blobs.emplace_back(P->off_cx, real(P->cx));
@@ -290,7 +312,8 @@ int build(lam_plan_s* P) {
   // kernel dimensions
   Dims& D = P->D;
   D.n0 = p.n0; D.n1 = p.n1; D.n2 = p.n2; D.h = p.h; D.w = p.w; D.ntheta = p.ntheta; D.m = m;
-  D.log2M0 = ilog2(P->M0); D.log2M1 = ilog2(P->M1); D.log2M2 = ilog2(P->M2);
+  D.M0 = P->M0; D.M1 = P->M1; D.M2 = P->M2;
+  D.lM0 = __builtin_ctz((unsigned)P->M0); D.lM1 = __builtin_ctz((unsigned)P->M1); D.lM2 = __builtin_ctz((unsigned)P->M2);
   D.beta = P->beta;
   D.xy.Rn2 = (double)R * p.n2;
   D.xy.Rn1 = (double)R * p.n1;
@@ -301,21 +324,21 @@ int build(lam_plan_s* P) {
   D.xy.h = p.h;
   // launch shapes
   LaunchCfg& c = P->cfg;
-  col_cfg(D.log2M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds);
+  col_cfg(P->M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds);
   // the z adjoint stages h samples per column in the same LDS, and both z kernels stage the per-row
   // bases and offsets and the inverse runs after it: shrink the tile until everything fits
   const size_t z_tables = (size_t)p.h * (sizeof(int) + P->rsize) + 2 * (size_t)P->M0 * sizeof(unsigned);
   while (c.z_log2TX > 0 && ((size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize > 131072 ||
                             (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize + z_tables > kLdsMax)) {
     --c.z_log2TX;
-    c.z_threads = (int)std::max<long>(64, ((long)P->M0 << c.z_log2TX) / vpt_of(P->csize));
+    c.z_threads = fft_threads(P->M0, 1L << c.z_log2TX, P->csize);
   }
   c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize + z_tables;
   if (c.z_lds > kLdsMax) return fail(LAM_ERR_ARG, "z kernels do not fit the LDS");
-  col_cfg(D.log2M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
-  row_cfg(D.log2M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
-  row_cfg(ilog2(p.w), p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
-  col_cfg(ilog2(p.h), p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
+  col_cfg(P->M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
+  row_cfg(P->M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
+  row_cfg(p.w, p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
+  col_cfg(p.h, p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
   c.g_log2TS = ilog2(TS);
   // gather: the tile plus its (2m-1) halo; scatter: two FP64 planes of the tile (pitch TS + 8)
   const size_t Pt = TS + 2 * m - 1;
@@ -332,6 +355,8 @@ Tables<T> tables(const lam_plan_s* P, const unsigned char* w) {
   Tables<T> t;
   t.tw = reinterpret_cast<const cpx<T>*>(w + P->off_tw);
   t.log2tw = ilog2(P->Ntw);
+  t.tw3 = P->Ntw3 ? reinterpret_cast<const cpx<T>*>(w + P->off_tw3) : nullptr;
+  t.log2tw3 = P->Ntw3 ? ilog2(P->Ntw3 / 3) : 0;
   t.cz = reinterpret_cast<const T*>(w + P->off_cz);
   t.cy = reinterpret_cast<const T*>(w + P->off_cy);
   t.cx = reinterpret_cast<const T*>(w + P->off_cx);
@@ -802,10 +827,10 @@ int lam_init(lam_plan* out, const lam_params* p) {
   if (!out || !p) return fail(LAM_ERR_ARG, "null argument");
   *out = nullptr;
   const char* bad = nullptr;
-  if (!is_pow2_in(p->n0, 16, 4096) || !is_pow2_in(p->n1, 16, 4096) || !is_pow2_in(p->n2, 16, 4096))
-    bad = "n0, n1, n2 must be powers of two in [16, 4096]";
-  else if (!is_pow2_in(p->h, 16, 4096) || !is_pow2_in(p->w, 16, 4096))
-    bad = "h, w must be powers of two in [16, 4096]";
+  if (!is_len_in(p->n0, 16, 4096) || !is_len_in(p->n1, 16, 4096) || !is_len_in(p->n2, 16, 4096))
+    bad = "n0, n1, n2 must be 2^k or 3 2^k in [16, 4096]";
+  else if (!is_len_in(p->h, 16, 4096) || !is_len_in(p->w, 16, 4096))
+    bad = "h, w must be 2^k or 3 2^k in [16, 4096]";
   else if (p->ntheta < 1 || p->ntheta > 4096) bad = "ntheta must be in [1, 4096]";
   else if (!(p->phi >= 0.0 && p->phi < M_PI / 2)) bad = "phi must be in [0, pi/2)";
   else if (p->oversample != 2) bad = "oversample must be 2";

@@ -1,5 +1,6 @@
 // Device building blocks for gfx950: complex arithmetic, an in-LDS batched
-// Stockham FFT (radix 8/4/2), and the Gaussian-gridding stencil.
+// Stockham FFT (radix 8/4/2, and a radix-3 stage for lengths 3 2^a), and the
+// Gaussian-gridding stencil.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -60,10 +61,27 @@ template <typename T> __device__ __forceinline__ void dft8(cpx<T>* v) {
   v[3] = e3 + o3; v[7] = e3 - o3;
 }
 
+// 3-point DFT: y0 = a0 + a1 + a2, y1,2 = a0 - (a1 + a2)/2 -/+ i sin(pi/3) (a1 - a2)
+template <typename T> __device__ __forceinline__ void dft3(cpx<T>* v) {
+  const T s = (T)0.86602540378443864676372317075293618;
+  const cpx<T> a0 = v[0], t = v[1] + v[2], d = v[1] - v[2];
+  const cpx<T> c = mk(a0.x - (T)0.5 * t.x, a0.y - (T)0.5 * t.y);
+  const cpx<T> r = mk(d.y * s, -d.x * s);          // -i sin(pi/3) (a1 - a2)
+  v[0] = a0 + t;
+  v[1] = c + r;
+  v[2] = c - r;
+}
+
 template <typename T, int R> __device__ __forceinline__ void dftR(cpx<T>* v) {
   if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 3) dft3(v);
   else if constexpr (R == 4) dft4(v);
   else dft8(v);
+}
+
+// floor(q / 3) for any 32-bit unsigned q: the high word of q (2^33 + 1) / 3, shifted once
+__host__ __device__ __forceinline__ int div3(int q) {
+  return (int)((unsigned)(((unsigned long long)(unsigned)q * 0xAAAAAAABull) >> 33));
 }
 
 // ---------------------------------------------------------------------------
@@ -163,6 +181,83 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int log2n, int log2nb, int 
     } else {
       fft_stage<T, 2, VPT, PAD>(buf, log2n, log2nb, Ns, lspan + 1, sp, sb, bfast, tw, log2tw, nth);
       Ns <<= 1; lspan += 1; rem -= 1;
+    }
+  }
+}
+
+// The same FFT for lengths N = 3 2^a (the grids of 3 2^k voxels): a radix-3
+// stage first (span 3, no twiddles), then radix 8/4/2 stages with Ns = 3 2^s
+// values already combined.  Index arithmetic divides by 3 with div3.  tw3[t]
+// = exp(-2 pi i t / Ntw3), Ntw3 = 3 2^log2tw3 >= N, so the twiddle of a stage
+// of span 3 2^(s + log2 R) sits at a stride 2^(log2tw3 - s - log2 R).  The
+// per-thread register arrays hold ceil(VPT / R) butterflies, which covers a
+// stage when nth >= N NB / VPT.
+template <typename T, int R, int VPT, bool PAD = false>
+__device__ __forceinline__ void fft_stage3(cpx<T>* buf, int a, int log2nb, int ls, int sp, int sb, bool bfast,
+                                           const cpx<T>* __restrict__ tw3, int log2tw3, int nth) {
+  constexpr int IT = (VPT + R - 1) / R;
+  constexpr int LR = R == 3 ? 0 : (R == 8 ? 3 : (R == 4 ? 2 : 1));
+  // butterflies per transform: N / 3 = 2^a for the radix-3 stage, N / R = 3 2^(a - LR) otherwise
+  const int la = a - LR, nbf = R == 3 ? (1 << a) : 3 << la;
+  const int total = nbf << log2nb;
+  const int tid = threadIdx.x;
+  auto map = [&](int t, int& j, int& b) {
+    if (bfast) { b = t & ((1 << log2nb) - 1); j = t >> log2nb; }
+    else if (R == 3) { j = t & (nbf - 1); b = t >> a; }
+    else { b = div3(t >> la); j = t - b * nbf; }
+  };
+  cpx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * nth;
+    if (t < total) {
+      int j, b;
+      map(t, j, b);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = buf[lpad<PAD>((j + r * nbf) * sp + b * sb)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * nth;
+    if (t < total) {
+      int j, b;
+      map(t, j, b);
+      int idxD, Ns;
+      if constexpr (R == 3) {          // Ns = 1: k = 0, outputs at 3 j + r
+        dft3(v[it]);
+        idxD = 3 * j;
+        Ns = 1;
+      } else {                         // Ns = 3 2^ls
+        const int hi = div3(j >> ls);
+        Ns = 3 << ls;
+        const int k = j - hi * Ns;
+        twiddle_dft<T, R>(v[it], tw3, k, log2tw3 - ls - LR);
+        idxD = hi * Ns * R + k;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lpad<PAD>((idxD + r * Ns) * sp + b * sb)] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int VPT, bool PAD = false>
+__device__ __forceinline__ void lds_fft3(cpx<T>* buf, int a, int log2nb, int sp, int sb, bool bfast,
+                                         const cpx<T>* __restrict__ tw3, int log2tw3, int nth) {
+  fft_stage3<T, 3, VPT, PAD>(buf, a, log2nb, 0, sp, sb, bfast, tw3, log2tw3, nth);
+  int ls = 0, rem = a;
+  while (rem > 0) {
+    if (rem >= 3) {
+      fft_stage3<T, 8, VPT, PAD>(buf, a, log2nb, ls, sp, sb, bfast, tw3, log2tw3, nth);
+      ls += 3; rem -= 3;
+    } else if (rem == 2) {
+      fft_stage3<T, 4, VPT, PAD>(buf, a, log2nb, ls, sp, sb, bfast, tw3, log2tw3, nth);
+      ls += 2; rem -= 2;
+    } else {
+      fft_stage3<T, 2, VPT, PAD>(buf, a, log2nb, ls, sp, sb, bfast, tw3, log2tw3, nth);
+      ls += 1; rem -= 1;
     }
   }
 }
@@ -272,11 +367,15 @@ struct XYGeom {
 // Contraction is off so the coordinate is the plain sequence of correctly
 // rounded products and sums: at angles where s lands on an integer (multiples
 // of pi/2), a fused multiply-add would round differently and move floor(s).
+// For the same reason k_u / w and k_v / h are correctly rounded quotients: the
+// product with 1/w is one only when w is a power of two (1/w exact); for
+// w = 3 2^k it can fall an ulp below an integer coordinate.
 __host__ __device__ inline void target_coords(const XYGeom& g, double ct, double st, int akv, int aku,
                                               double& sx, double& sy) {
 #pragma clang fp contract(off)
-  const double ku = (double)(aku - g.w / 2) * g.inv_w;
-  const double kv = (double)(akv - g.h / 2) * g.inv_h;
+  const double nu = (double)(aku - g.w / 2), nv = (double)(akv - g.h / 2);
+  const double ku = (g.w & (g.w - 1)) == 0 ? nu * g.inv_w : nu / (double)g.w;
+  const double kv = (g.h & (g.h - 1)) == 0 ? nv * g.inv_h : nv / (double)g.h;
   sx = g.Rn2 * (ku * ct + kv * g.sphi * st);
   sy = g.Rn1 * (ku * st - kv * g.sphi * ct);
 }

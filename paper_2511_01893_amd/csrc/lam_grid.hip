@@ -59,7 +59,7 @@ __device__ __forceinline__ void band_targets(const Dims& D, const double* cth, c
 // counts[k][ty][tx][class] for the slices [k0, k0 + gridDim.y), tile row blockIdx.x
 template <typename T, int MH>
 __global__ __launch_bounds__(256) void k_list_count(Dims D, Tables<T> tb, int log2TS, int k0, int* __restrict__ counts) {
-  const int ntx = (1 << D.log2M2) >> log2TS, nty = (1 << D.log2M1) >> log2TS;
+  const int ntx = D.M2 >> log2TS, nty = D.M1 >> log2TS;
   const int ty = blockIdx.x, k = k0 + blockIdx.y;
   int* cnt = reinterpret_cast<int*>(lam_smem);                 // [ntx * 9]
   for (int i = threadIdx.x; i < ntx * 9; i += blockDim.x) cnt[i] = 0;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_list_count(Dims D, Tables<T> tb, int lo
 template <typename T, int MH>
 __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log2TS, int k0, const int* __restrict__ offs,
                                                    int* __restrict__ lists) {
-  const int ntx = (1 << D.log2M2) >> log2TS, nty = (1 << D.log2M1) >> log2TS;
+  const int ntx = D.M2 >> log2TS, nty = D.M1 >> log2TS;
   const int ty = blockIdx.x, k = k0 + blockIdx.y;
   int* cur = reinterpret_cast<int*>(lam_smem);                 // [ntx * 9]
   const size_t per_slice = (size_t)ntx * nty * 9 + 1;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log
 template <typename T, int MH>
 __global__ __launch_bounds__(256) void k_list_check(Dims D, Tables<T> tb, int log2TS, int k0,
                                                     unsigned* __restrict__ seen, int* __restrict__ bad) {
-  const int ntx = (1 << D.log2M2) >> log2TS, nty = (1 << D.log2M1) >> log2TS;
+  const int ntx = D.M2 >> log2TS, nty = D.M1 >> log2TS;
   const int tile = blockIdx.x, k = k0 + blockIdx.y, tx = tile % ntx, ty = tile / ntx;
   const int* of = tb.toff + (size_t)k * ((size_t)ntx * nty * 9 + 1) + (size_t)tile * 9;
   const int* L = tb.tlist + (size_t)k * D.ntheta * D.w;
@@ -254,23 +254,27 @@ __device__ __forceinline__ void fgg_taps(const Fgg<T>& g, T d, T* w) {
   }
 }
 
-// Position v relative to a tile origin, folded by the grid period M into
+// Position v (-2M <= v < 2M) relative to a tile origin, folded by the grid period M into
 // [-16, M - 16): with TS + 16 <= M and at most 16 taps, a stencil point lies in
-// the tile exactly when its folded position is in [0, TS).
+// the tile exactly when its folded position is in [0, TS).  P2: M is a power of two.
+template <bool P2>
 __device__ __forceinline__ int fold_rel(int v, int M) {
-  const int r = v & (M - 1);
+  const int r = wrap2<P2>(v, M);
   return r >= M - 16 ? r - M : r;
 }
 
 // ---------------------------------------------------------------------------
 // F_u2D gather over one tile of the oversampled grid
 // ---------------------------------------------------------------------------
-template <typename T, int MH>
+// P2: M1 and M2 are powers of two (index masks); otherwise either may be 3 2^k (compares).  Target
+// coordinates satisfy |s| < 0.71 M (|k_u|, |k_v| <= 1/2 of the detector, sin(phi) < 1), so a base
+// relative to a tile origin lies in (-2M, M).
+template <typename T, int MH, bool P2>
 __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, cpx<T>* out, const cpx<T>* dhat, int k0,
                                                 Dims D, Tables<T> tb, int log2TS) {
   constexpr int W = 2 * MH;
   const int TS = 1 << log2TS, P = TS + W - 1;
-  const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
+  const int M1 = D.M1, M2 = D.M2;
   const int ntx = M2 >> log2TS, nty = M1 >> log2TS;
   const int tid = threadIdx.x, nth = blockDim.x;
   cpx<T>* tile = reinterpret_cast<cpx<T>*>(lam_smem);
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
     for (int it = 0; it < vpt<T>(); ++it) {
       const int e = min(e0 + tid + it * nth, P * P - 1);
       const int r = (int)(((unsigned long long)(unsigned)e * magicP) >> 32), c = e - r * P;
-      v[it] = G[(size_t)((y0 - MH + 1 + r) & (M1 - 1)) * M2 + ((x0 - MH + 1 + c) & (M2 - 1))];
+      v[it] = G[(size_t)wrap1<P2>(y0 - MH + 1 + r, M1) * M2 + wrap1<P2>(x0 - MH + 1 + c, M2)];
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
       T wx[W], wy[W];
       fgg_taps<T, MH>(fg, (T)(sx - fx), wx);
       fgg_taps<T, MH>(fg, (T)(sy - fy), wy);
-      const int ox = (bx - x0) & (M2 - 1), oy = (by - y0) & (M1 - 1);
+      const int ox = wrap2<P2>(bx - x0, M2), oy = wrap2<P2>(by - y0, M1);
       T ax = 0, ay = 0;
 #pragma unroll
       for (int iy = 0; iy < W; ++iy) {
@@ -371,7 +375,7 @@ __global__ __launch_bounds__(256) void k_gather(const cpx<T>* __restrict__ Gb, c
 // row evaluate their own targets as before, trade what the other needs through DPP, and then
 // add both targets in turn: lane (h, j) adds column j of the rows of parity h.
 // ---------------------------------------------------------------------------
-template <typename T, int MH, int LTS = 0, bool PAIRS = false>
+template <typename T, int MH, bool P2, int LTS = 0, bool PAIRS = false>
 __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ Gb, int k0,
                                                  Dims D, Tables<T> tb, int log2TS_) {
   constexpr int W = 2 * MH, GW = group_width<MH>(), NG = 64 / GW;
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
   static_assert(PAIRS == (LTS > 0) && (!PAIRS || MH == 4), "the folded path is the row-pair path, m = 4");
   const int log2TS = LTS > 0 ? LTS : log2TS_;
   const int TS = 1 << log2TS, PA = TS + 8;   // PA = 8 (mod 32): stencil rows of a target fall in distinct banks
-  const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
+  const int M1 = D.M1, M2 = D.M2;
   const int ntx = M2 >> log2TS, nty = M1 >> log2TS;
   const int tid = threadIdx.x, nth = blockDim.x;
   double* are = reinterpret_cast<double*>(lam_smem);           // [TS][PA]
@@ -427,8 +431,8 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
         double sx, sy;
         target_coords(D.xy, tb.cth[ts], tb.sth[ts], k, uks, sx, sy);
         const double fy = floor(sy), fx = floor(sx);
-        const int c0s = oks ? fold_rel((int)fx - MH + 1 - x0, M2) : TS;   // TS: no target
-        const int r0s = fold_rel((int)fy - MH + 1 - y0, M1);
+        const int c0s = oks ? fold_rel<P2>((int)fx - MH + 1 - x0, M2) : TS;   // TS: no target
+        const int r0s = fold_rel<P2>((int)fy - MH + 1 - y0, M1);
         const T dxs = (T)(sx - fx);
         // row weights by parity, from d = delta_y: odd rows start at the centre row m - 1
         // (offset d), even rows at row m - 2 (offset d + 1); two-row ratios up and down.  The
@@ -506,13 +510,13 @@ __global__ __launch_bounds__(512) void k_scatter(const cpx<T>* __restrict__ in, 
           target_coords(D.xy, c[u], sn[u], k, uk[u], sx, sy);
           const double fy = floor(sy), fx = floor(sx);
           const int by = (int)fy, bx = (int)fx;
-          const int col = (bx - MH + 1 + j - x0) & (M2 - 1), r0 = by - MH + 1 - y0;
+          const int col = wrap2<P2>(bx - MH + 1 + j - x0, M2), r0 = by - MH + 1 - y0;
           if (ok[u] && j < W && (unsigned)col < (unsigned)TS) {
             const T wxj = fg.one((T)(sx - fx) - (T)(j + 1 - MH));
             T wc, up, dn;
             fg.seeds((T)(sy - fy), wc, up, dn);
             auto add = [&](int iy, double x, double y) {
-              const int row = (r0 + iy) & (M1 - 1);
+              const int row = wrap2<P2>(r0 + iy, M1);
               if (row >= TS) return;
               const int a = __umul24(row, PA) + col;
               atomicAdd(are + a, x);
@@ -603,12 +607,12 @@ constexpr int fx_pitch() { return 64 + 2 * (2 * MH - 1); }
 template <int MH>
 constexpr size_t fx_lds() { return (size_t)fx_pitch<MH>() * fx_pitch<MH>() * 8 + 64 * 8 + 16; }
 
-template <int MH>
+template <int MH, bool P2>
 __global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict__ in, cpx<float>* __restrict__ Gb,
                                                     int k0, Dims D, Tables<float> tb) {
   constexpr int W = 2 * MH, GD = W - 1, PT = fx_pitch<MH>(), TS = 64, LTS = 6, GW = 8, NG = 64 / GW;
   static_assert(W <= GW, "one lane per stencil column");
-  const int M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
+  const int M1 = D.M1, M2 = D.M2;
   const int ntx = M2 >> LTS, nty = M1 >> LTS;
   const int tid = threadIdx.x, nth = blockDim.x;
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(lam_smem);   // [PT][PT], cell (r, c) at (r + GD) PT + c + GD
@@ -648,8 +652,8 @@ __global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict
     const cpx<float> v = in[(size_t)t * hw + (unsigned)(kw + uk)];
     double sx, sy;
     target_coords(D.xy, tb.cth[t], tb.sth[t], k, uk, sx, sy);
-    const int bx = min(max(fold_rel((int)floor(sx) - x0, M2) >> 3, 0), 7);
-    const int by = min(max(fold_rel((int)floor(sy) - y0, M1) >> 3, 0), 7);
+    const int bx = min(max(fold_rel<P2>((int)floor(sx) - x0, M2) >> 3, 0), 7);
+    const int by = min(max(fold_rel<P2>((int)floor(sy) - y0, M1) >> 3, 0), 7);
     atomicAdd(blk + by * 8 + bx, (double)fmaxf(fabsf(v.x), fabsf(v.y)));
   }
   __syncthreads();
@@ -696,7 +700,8 @@ __global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict
       target_coords(D.xy, tb.cth[ts], tb.sth[ts], k, uks, sx, sy);
       const double fy = floor(sy), fx = floor(sx);
       // address of the stencil's first cell, -1: no target
-      const int as = oks ? __umul24(fold_rel((int)fy - MH + 1 - y0, M1) + GD, PT) + fold_rel((int)fx - MH + 1 - x0, M2) + GD
+      const int as = oks ? __umul24(fold_rel<P2>((int)fy - MH + 1 - y0, M1) + GD, PT) +
+                               fold_rel<P2>((int)fx - MH + 1 - x0, M2) + GD
                          : -1;
       const float dxs = (float)(sx - fx);
       float wys[W];
@@ -746,7 +751,9 @@ __global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict
 // ---------------------------------------------------------------------------
 namespace {
 // 64 x 64 tiles on a grid of at least 128 x 128: the compile-time tile kernels apply
-bool fast_tiles(const LaunchCfg& c, const Dims& D) { return c.g_log2TS == 6 && D.log2M1 >= 7 && D.log2M2 >= 7; }
+bool fast_tiles(const LaunchCfg& c, const Dims& D) { return c.g_log2TS == 6 && D.M1 >= 128 && D.M2 >= 128; }
+// both grid periods are powers of two: the tile kernels index with masks
+bool pow2_grid(const Dims& D) { return (D.M1 & (D.M1 - 1)) == 0 && (D.M2 & (D.M2 - 1)) == 0; }
 
 template <typename Kern>
 hipError_t prep(Kern k, size_t lds) {
@@ -771,7 +778,7 @@ hipError_t prep(Kern k, size_t lds) {
 template <typename T>
 hipError_t launch_list_count(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, int* counts,
                              hipStream_t s) {
-  const int ntx = (1 << D.log2M2) >> c.g_log2TS, nty = (1 << D.log2M1) >> c.g_log2TS;
+  const int ntx = D.M2 >> c.g_log2TS, nty = D.M1 >> c.g_log2TS;
   LAM_MH_SWITCH(D.m, {
     hipLaunchKernelGGL((k_list_count<T, MH>), dim3(nty, ns), dim3(256), ntx * 9 * sizeof(int), s, D, tb, c.g_log2TS,
                        k0, counts);
@@ -782,7 +789,7 @@ hipError_t launch_list_count(const LaunchCfg& c, int k0, int ns, const Dims& D, 
 template <typename T>
 hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, const int* offs,
                             int* lists, hipStream_t s) {
-  const int ntx = (1 << D.log2M2) >> c.g_log2TS, nty = (1 << D.log2M1) >> c.g_log2TS;
+  const int ntx = D.M2 >> c.g_log2TS, nty = D.M1 >> c.g_log2TS;
   LAM_MH_SWITCH(D.m, {
     hipLaunchKernelGGL((k_list_fill<T, MH>), dim3(nty, ns), dim3(256), ntx * 9 * sizeof(int), s, D, tb, c.g_log2TS,
                        k0, offs, lists);
@@ -793,7 +800,7 @@ hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, c
 template <typename T>
 hipError_t launch_list_check(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, unsigned* seen,
                              int* bad, hipStream_t s) {
-  const int ntx = (1 << D.log2M2) >> c.g_log2TS, nty = (1 << D.log2M1) >> c.g_log2TS;
+  const int ntx = D.M2 >> c.g_log2TS, nty = D.M1 >> c.g_log2TS;
   LAM_MH_SWITCH(D.m, {
     hipLaunchKernelGGL((k_list_check<T, MH>), dim3(ntx * nty, ns), dim3(256), 0, s, D, tb, c.g_log2TS, k0, seen,
                        bad);
@@ -806,9 +813,9 @@ hipError_t launch_gather(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* out, cons
                          const Dims& D, const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
-    auto k = k_gather<T, MH>;
+    auto k = pow2_grid(D) ? k_gather<T, MH, true> : k_gather<T, MH, false>;
     if ((e = prep(k, c.g_lds)) != hipSuccess) return e;
-    const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
+    const int ntiles = (D.M2 >> c.g_log2TS) * (D.M1 >> c.g_log2TS);
     hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.g_threads), c.g_lds, s, Gb, out, dhat, k0, D, tb, c.g_log2TS);
   });
   return hipGetLastError();
@@ -818,19 +825,20 @@ template <typename T>
 hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int k0, int ns, const Dims& D,
                           const Tables<T>& tb, hipStream_t s) {
   hipError_t e = hipSuccess;
-  const int ntiles = ((1 << D.log2M2) >> c.g_log2TS) * ((1 << D.log2M1) >> c.g_log2TS);
+  const int ntiles = (D.M2 >> c.g_log2TS) * (D.M1 >> c.g_log2TS);
+  const bool p2 = pow2_grid(D);
   LAM_MH_SWITCH(D.m, {
     if constexpr (std::is_same<T, float>::value && MH <= 4) {
       if (fast_tiles(c, D)) {   // complex64: fixed-point accumulation
-        auto kf = k_scatter_fx<MH>;
+        auto kf = p2 ? k_scatter_fx<MH, true> : k_scatter_fx<MH, false>;
         if ((e = prep(kf, fx_lds<MH>())) != hipSuccess) return e;
         hipLaunchKernelGGL(kf, dim3(ntiles * ns), dim3(512), fx_lds<MH>(), s, in, Gb, k0, D, tb);
         return hipGetLastError();
       }
     }
-    auto k = k_scatter<T, MH>;
+    auto k = p2 ? k_scatter<T, MH, true> : k_scatter<T, MH, false>;
     if constexpr (MH == 4)
-      if (fast_tiles(c, D)) k = k_scatter<T, MH, 6, true>;
+      if (fast_tiles(c, D)) k = p2 ? k_scatter<T, MH, true, 6, true> : k_scatter<T, MH, false, 6, true>;
     if ((e = prep(k, c.s_lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(ntiles * ns), dim3(c.s_threads), c.s_lds, s, in, Gb, k0, D, tb, c.g_log2TS);
   });

@@ -15,20 +15,42 @@ struct SkipMap {
   __device__ __forceinline__ bool skip(int unit) const { return hit && hit[(unit + off) >> log2chunk]; }
 };
 
-// Sizes passed by value to every kernel.
+// Sizes passed by value to every kernel.  Every transform length (the oversampled grids M0, M1, M2
+// and the detector h, w) is 2^l or 3 2^l; lM* is that l (the count of trailing zero bits).
 struct Dims {
   int n0, n1, n2, h, w, ntheta, m;
-  int log2M0, log2M1, log2M2;
+  int M0, M1, M2;
+  int lM0, lM1, lM2;
   double beta;      // Gaussian exponent in grid units, pi (R - 1/2) / (R m)
   XYGeom xy;
   SkipMap skip;     // memoized chunks (lam_admm_step_memo); empty otherwise
+  // slice of row r of a slab of M1-row grids
+  __device__ __forceinline__ int slice_of(int r) const { return M1 == (1 << lM1) ? r >> lM1 : div3(r >> lM1); }
 };
+
+// Periodic index arithmetic on a grid of M points: P2 when M is a power of two (a mask), otherwise
+// M = 3 2^k (compares and selects).  wrap1 takes -M <= v < 2M, wrap2 -2M <= v < 2M.
+template <bool P2> __host__ __device__ __forceinline__ int wrap1(int v, int M) {
+  if constexpr (P2) return v & (M - 1);
+  else return v < 0 ? v + M : (v >= M ? v - M : v);
+}
+template <bool P2> __host__ __device__ __forceinline__ int wrap2(int v, int M) {
+  if constexpr (P2) return v & (M - 1);
+  else {
+    v = v < 0 ? v + 2 * M : v;
+    return v >= M ? v - M : v;
+  }
+}
+// e / N and N = 2^l (P2) or 3 2^l
+template <bool P2> __device__ __forceinline__ int div_len(int e, int l) { return P2 ? e >> l : div3(e >> l); }
 
 // Device tables (inside the caller's workspace), built in FP64 on the host.
 template <typename T>
 struct Tables {
-  const cpx<T>* tw;   // exp(-2 pi i t / 2^log2tw)
+  const cpx<T>* tw;   // exp(-2 pi i t / 2^log2tw): the power-of-two transforms
   int log2tw;
+  const cpx<T>* tw3;  // exp(-2 pi i t / (3 2^log2tw3)): the 3 2^k transforms (null when the plan has none)
+  int log2tw3;
   const T* cz;        // deconvolution factors along z, y, x
   const T* cy;
   const T* cx;

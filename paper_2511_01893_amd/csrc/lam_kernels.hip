@@ -24,7 +24,8 @@ extern __shared__ __align__(16) unsigned char lam_smem[];
 __device__ __forceinline__ int sgn_parity(int k) { return (k & 1) ? -1 : 1; }
 
 // The FFT kernels take template sizes LN (log2 of the transform length) and LB (log2 of the
-// transforms per block): LN = 0 selects the general kernel (sizes from the arguments); otherwise the
+// transforms per block): LN = 0 selects the general kernel for power-of-two lengths (sizes from the
+// arguments), LN = -1 the general kernel for lengths 3 2^l (the mixed-radix LDS FFT); otherwise the
 // sizes are compile-time constants (the hot sizes) and the compile-time LDS FFT runs.
 template <typename T, int LN, int LB> constexpr int ct_threads() {
   return ((1 << (LN + LB)) / vpt<T>()) < 64 ? 64 : ((1 << (LN + LB)) / vpt<T>());
@@ -33,17 +34,19 @@ template <typename T, int LN, int LB> __device__ __forceinline__ int block_threa
   if constexpr (LN > 0) return ct_threads<T, LN, LB>();
   else return (int)blockDim.x;
 }
-// column blocks: element (p, b) at p 2^log2TX + b
+// column blocks: element (p, b) at p 2^log2TX + b; the length is 2^lN, or 3 2^lN for LN = -1
 template <typename T, int LN, int LB>
-__device__ __forceinline__ void fft_cols(cpx<T>* buf, int log2N, int log2TX, const Tables<T>& tb, int nth) {
+__device__ __forceinline__ void fft_cols(cpx<T>* buf, int lN, int log2TX, const Tables<T>& tb, int nth) {
   if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), false, LN, LB, true>(buf, tb.tw, tb.log2tw);
-  else lds_fft<T, vpt<T>()>(buf, log2N, log2TX, 1 << log2TX, 1, true, tb.tw, tb.log2tw, nth);
+  else if constexpr (LN < 0) lds_fft3<T, vpt<T>()>(buf, lN, log2TX, 1 << log2TX, 1, true, tb.tw3, tb.log2tw3, nth);
+  else lds_fft<T, vpt<T>()>(buf, lN, log2TX, 1 << log2TX, 1, true, tb.tw, tb.log2tw, nth);
 }
-// row blocks: element (p, b) at b 2^log2N + p, one pad slot per 8 elements
+// row blocks: element (p, b) at b N + p, one pad slot per 8 elements; N = 2^lN, or 3 2^lN for LN = -1
 template <typename T, int LN, int LB>
-__device__ __forceinline__ void fft_rows(cpx<T>* buf, int log2N, int log2RB, const Tables<T>& tb, int nth) {
+__device__ __forceinline__ void fft_rows(cpx<T>* buf, int lN, int N, int log2RB, const Tables<T>& tb, int nth) {
   if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), true, LN, LB, false>(buf, tb.tw, tb.log2tw);
-  else lds_fft<T, vpt<T>(), true>(buf, log2N, log2RB, 1, 1 << log2N, false, tb.tw, tb.log2tw, nth);
+  else if constexpr (LN < 0) lds_fft3<T, vpt<T>(), true>(buf, lN, log2RB, 1, N, false, tb.tw3, tb.log2tw3, nth);
+  else lds_fft<T, vpt<T>(), true>(buf, lN, log2RB, 1, N, false, tb.tw, tb.log2tw, nth);
 }
 
 // ---------------------------------------------------------------------------
@@ -53,8 +56,9 @@ template <typename T, int MH, bool REAL_IN, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx<T>* __restrict__ u1, Dims D,
                                                Tables<T> tb, int log2TX_, int y0, size_t in_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2TX = LN > 0 ? LB : log2TX_, log2M0 = LN > 0 ? LN : D.log2M0;
-  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
+  constexpr bool P2 = LN >= 0;
+  const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? LN : D.lM0;
+  const int TX = 1 << log2TX, M0 = LN > 0 ? 1 << LN : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // blockIdx.y is the row within the input slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   if (D.skip.skip(y)) return;
@@ -87,12 +91,12 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
       const int e = tid + it * nth;
       if (e < n0 * TX) {
         const int a = e >> log2TX, b = e & (TX - 1);
-        buf[((a - n0 / 2) & (M0 - 1)) * TX + b] = v[it] * tb.cz[a];
+        buf[wrap1<P2>(a - n0 / 2, M0) * TX + b] = v[it] * tb.cz[a];
       }
     }
   }
   __syncthreads();
-  fft_cols<T, LN, LB>(buf, log2M0, log2TX, tb, nth);
+  fft_cols<T, LN, LB>(buf, lM0, log2TX, tb, nth);
   const GaussW gw{D.beta};
   for (int e = tid; e < D.h * TX; e += nth) {
     const int av = e >> log2TX, b = e & (TX - 1);
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
 #pragma unroll
     for (int i = 0; i < 2 * MH; ++i) {
       const T w = gw(dl - (T)(i + 1 - MH), T());
-      const cpx<T> g = buf[((base + i) & (M0 - 1)) * TX + b];
+      const cpx<T> g = buf[wrap1<P2>(base + i, M0) * TX + b];
       ax += w * g.x;
       ay += w * g.y;
     }
@@ -121,8 +125,9 @@ template <typename T, int MH, bool REAL_OUT, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, void* __restrict__ uout, Dims D,
                                                Tables<T> tb, int log2TX_, int y0, size_t out_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2TX = LN > 0 ? LB : log2TX_, log2M0 = LN > 0 ? LN : D.log2M0;
-  const int TX = 1 << log2TX, M0 = 1 << log2M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
+  constexpr bool P2 = LN >= 0;
+  const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? LN : D.lM0;
+  const int TX = 1 << log2TX, M0 = LN > 0 ? 1 << LN : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // blockIdx.y is the row within the output slab; y the row of the volume
   const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
   if (D.skip.skip(y)) return;
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
         const int a0 = (int)(run & 0xffffu), a1 = a0 + (int)(run >> 16);
         for (int av = a0; av < a1; ++av) {
           // the stencil tap of row av that lands on q
-          const int i = (q - zb[av] + MH - 1) & (M0 - 1);
+          const int i = wrap1<P2>(q - zb[av] + MH - 1, M0);
           const T w = gw(zd[av] - (T)(i + 1 - MH), T());
           const cpx<T> g = buf[av * TX + b];
           ax += w * g.x;
@@ -186,10 +191,10 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
     if (e < total) buf[e] = v[it];
   }
   __syncthreads();
-  fft_cols<T, LN, LB>(buf, log2M0, log2TX, tb, nth);
+  fft_cols<T, LN, LB>(buf, lM0, log2TX, tb, nth);
   for (int e = tid; e < n0 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
-    const cpx<T> g = buf[((a - n0 / 2) & (M0 - 1)) * TX + b];
+    const cpx<T> g = buf[wrap1<P2>(a - n0 / 2, M0) * TX + b];
     const T c = tb.cz[a];
     const size_t gi = (size_t)a * out_zs + (size_t)yl * D.n2 + x0 + b;
     if constexpr (REAL_OUT) reinterpret_cast<T*>(uout)[gi] = g.x * c;
@@ -204,8 +209,9 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1, cpx<T>* __restrict__ Tb, int k0,
                                                    Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
-  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
+  constexpr bool P2 = LN >= 0;
+  const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? LN : D.lM1;
+  const int TX = 1 << log2TX, M1 = LN > 0 ? 1 << LN : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
   if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -225,12 +231,12 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
       const int e = tid + it * nth;
       if (e < n1 * TX) {
         const int a = e >> log2TX, b = e & (TX - 1);
-        buf[((a - n1 / 2) & (M1 - 1)) * TX + b] = v[it] * (tb.cy[a] * tb.cx[x0 + b]);
+        buf[wrap1<P2>(a - n1 / 2, M1) * TX + b] = v[it] * (tb.cy[a] * tb.cx[x0 + b]);
       }
     }
   }
   __syncthreads();
-  fft_cols<T, LN, LB>(buf, log2M1, log2TX, tb, nth);
+  fft_cols<T, LN, LB>(buf, lM1, log2TX, tb, nth);
   for (int e = tid; e < M1 * TX; e += nth) {
     const int q = e >> log2TX, b = e & (TX - 1);
     Tb[((size_t)kk * M1 + q) * n2 + x0 + b] = buf[e];
@@ -241,8 +247,9 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb, cpx<T>* __restrict__ u1, int k0,
                                                    Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2TX = LN > 0 ? LB : log2TX_, log2M1 = LN > 0 ? LN : D.log2M1;
-  const int TX = 1 << log2TX, M1 = 1 << log2M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
+  constexpr bool P2 = LN >= 0;
+  const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? LN : D.lM1;
+  const int TX = 1 << log2TX, M1 = LN > 0 ? 1 << LN : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
   if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -260,10 +267,10 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
     }
   }
   __syncthreads();
-  fft_cols<T, LN, LB>(buf, log2M1, log2TX, tb, nth);
+  fft_cols<T, LN, LB>(buf, lM1, log2TX, tb, nth);
   for (int e = tid; e < n1 * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
-    const cpx<T> v = buf[((a - n1 / 2) & (M1 - 1)) * TX + b];
+    const cpx<T> v = buf[wrap1<P2>(a - n1 / 2, M1) * TX + b];
     const T c = tb.cy[a] * tb.cx[x0 + b];
     u1[((size_t)k * n1 + a) * n2 + x0 + b] = mk(v.x * c, -v.y * c);
   }
@@ -273,10 +280,11 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb, cpx<T>* __restrict__ Gb, Dims D,
                                                    Tables<T> tb, int log2RB_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2RB = LN > 0 ? LB : log2RB_, log2M2 = LN > 0 ? LN : D.log2M2;
-  const int RB = 1 << log2RB, M2 = 1 << log2M2, n2 = M2 / 2, log2n2 = log2M2 - 1;
-  const size_t r0 = (size_t)blockIdx.x * RB;
-  if (D.skip.skip((int)(r0 >> D.log2M1))) return;
+  constexpr bool P2 = LN >= 0;
+  const int log2RB = LN > 0 ? LB : log2RB_, lM2 = LN > 0 ? LN : D.lM2;
+  const int RB = 1 << log2RB, M2 = LN > 0 ? 1 << LN : D.M2, n2 = M2 / 2, ln2 = lM2 - 1;
+  const int r0 = blockIdx.x * RB;   // slab rows: at most h M1 < 2^31
+  if (D.skip.hit && D.skip.skip(D.slice_of(r0))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
   // R = 2: the padded positions of each row are [n2/2, M2 - n2/2), n2 of them
@@ -286,39 +294,40 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
     for (int it = 0; it < vpt<T>(); ++it) {
       if (it * nth >= RB * n2) break;   // the input fills n2 of the M2 points of each row
       const int e = min(tid + it * nth, RB * n2 - 1);
-      v[it] = Tb[r0 * n2 + e];
+      v[it] = Tb[(size_t)r0 * n2 + e];
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
       if (it * nth >= RB * n2) break;
       const int e = tid + it * nth;
       if (e < RB * n2) {
-        const int b = e >> log2n2, a = e & (n2 - 1);
+        const int b = div_len<P2>(e, ln2), a = e - b * n2;
         buf[lpad<true>(b * M2 + n2 / 2 + a)] = zero;
-        buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))] = v[it];
+        buf[lpad<true>(b * M2 + wrap1<P2>(a - n2 / 2, M2))] = v[it];
       }
     }
   }
   __syncthreads();
-  fft_rows<T, LN, LB>(buf, log2M2, log2RB, tb, nth);
-  for (int e = tid; e < RB * M2; e += nth) Gb[r0 * M2 + e] = buf[lpad<true>(e)];
+  fft_rows<T, LN, LB>(buf, lM2, M2, log2RB, tb, nth);
+  for (int e = tid; e < RB * M2; e += nth) Gb[(size_t)r0 * M2 + e] = buf[lpad<true>(e)];
 }
 
 template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb, cpx<T>* __restrict__ Tb, Dims D,
                                                    Tables<T> tb, int log2RB_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2RB = LN > 0 ? LB : log2RB_, log2M2 = LN > 0 ? LN : D.log2M2;
-  const int RB = 1 << log2RB, M2 = 1 << log2M2, n2 = M2 / 2, log2n2 = log2M2 - 1;
-  const size_t r0 = (size_t)blockIdx.x * RB;
-  if (D.skip.skip((int)(r0 >> D.log2M1))) return;
+  constexpr bool P2 = LN >= 0;
+  const int log2RB = LN > 0 ? LB : log2RB_, lM2 = LN > 0 ? LN : D.lM2;
+  const int RB = 1 << log2RB, M2 = LN > 0 ? 1 << LN : D.M2, n2 = M2 / 2, ln2 = lM2 - 1;
+  const int r0 = blockIdx.x * RB;   // slab rows: at most h M1 < 2^31
+  if (D.skip.hit && D.skip.skip(D.slice_of(r0))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> v[vpt<T>()];
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
       const int e = min(tid + it * nth, RB * M2 - 1);
-      v[it] = Gb[r0 * M2 + e];
+      v[it] = Gb[(size_t)r0 * M2 + e];
     }
 #pragma unroll
     for (int it = 0; it < vpt<T>(); ++it) {
@@ -327,28 +336,29 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
     }
   }
   __syncthreads();
-  fft_rows<T, LN, LB>(buf, log2M2, log2RB, tb, nth);
+  fft_rows<T, LN, LB>(buf, lM2, M2, log2RB, tb, nth);
   for (int e = tid; e < RB * n2; e += nth) {
-    const int b = e >> log2n2, a = e & (n2 - 1);
-    Tb[(r0 + b) * n2 + a] = conj(buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))]);
+    const int b = div_len<P2>(e, ln2), a = e - b * n2;
+    Tb[((size_t)r0 + b) * n2 + a] = conj(buf[lpad<true>(b * M2 + wrap1<P2>(a - n2 / 2, M2))]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Centred 2D DFT per projection: row pass (along k_u / p) and column pass
 // (along k_v / v).  Centring is the checkerboard (-1)^(row+col) applied
-// before the row pass and after the column pass (h, w multiples of 4).
+// before the row pass and after the column pass (h, w multiples of 4; h even,
+// so the parity of a row within its projection is that of its slab row).
 // The inverse transform is conj(FFT(conj(.))).
 // ---------------------------------------------------------------------------
 template <typename T, int LN = 0, int LB = 0>
-__global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, int log2L_,
-                                                 int log2h, int log2RB_, int inverse, Tables<T> tb) {
+__global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, int L_, int lL_, int log2RB_,
+                                                 int inverse, Tables<T> tb) {
+  constexpr bool P2 = LN >= 0;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2RB = LN > 0 ? LB : log2RB_, log2L = LN > 0 ? LN : log2L_;
-  const int RB = 1 << log2RB, L = 1 << log2L;
+  const int log2RB = LN > 0 ? LB : log2RB_, lL = LN > 0 ? LN : lL_;
+  const int RB = 1 << log2RB, L = LN > 0 ? 1 << LN : L_;
   const size_t r0 = (size_t)blockIdx.x * RB;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
-  const int hmask = (1 << log2h) - 1;
   {
     cpx<T> w[vpt<T>()];
 #pragma unroll
@@ -360,15 +370,14 @@ __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, 
     for (int it = 0; it < vpt<T>(); ++it) {
       const int e = tid + it * nth;
       if (e < RB * L) {
-        const int b = e >> log2L, p = e & (L - 1);
-        const int arow = (int)((r0 + b) & hmask);
+        const int b = div_len<P2>(e, lL), p = e - b * L;
         cpx<T> v = inverse ? conj(w[it]) : w[it];
-        buf[lpad<true>(e)] = sgn_parity(arow + p) > 0 ? v : mk(-v.x, -v.y);
+        buf[lpad<true>(e)] = sgn_parity((int)(r0 & 1) + b + p) > 0 ? v : mk(-v.x, -v.y);
       }
     }
   }
   __syncthreads();
-  fft_rows<T, LN, LB>(buf, log2L, log2RB, tb, nth);
+  fft_rows<T, LN, LB>(buf, lL, L, log2RB, tb, nth);
   for (int e = tid; e < RB * L; e += nth) {
     const cpx<T> v = buf[lpad<true>(e)];
     out[r0 * L + e] = inverse ? conj(v) : v;
@@ -376,11 +385,11 @@ __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, 
 }
 
 template <typename T, int LN = 0, int LB = 0>
-__global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, int log2h_,
-                                                 int log2w, int log2TX_, int inverse, T scale, Tables<T> tb) {
+__global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, int H_, int lH_, int W,
+                                                 int log2TX_, int inverse, T scale, Tables<T> tb) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2TX = LN > 0 ? LB : log2TX_, log2h = LN > 0 ? LN : log2h_;
-  const int TX = 1 << log2TX, H = 1 << log2h, W = 1 << log2w;
+  const int log2TX = LN > 0 ? LB : log2TX_, lH = LN > 0 ? LN : lH_;
+  const int TX = 1 << log2TX, H = LN > 0 ? 1 << LN : H_;
   const int p0 = blockIdx.x * TX;
   const size_t base = (size_t)blockIdx.y * H * W;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -398,7 +407,7 @@ __global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, 
     }
   }
   __syncthreads();
-  fft_cols<T, LN, LB>(buf, log2h, log2TX, tb, nth);
+  fft_cols<T, LN, LB>(buf, lH, log2TX, tb, nth);
   for (int e = tid; e < H * TX; e += nth) {
     const int a = e >> log2TX, b = e & (TX - 1);
     cpx<T> v = buf[e];
@@ -431,7 +440,8 @@ static hipError_t prep(Kern k, size_t lds) {
   }
 
 // Compile-time-size kernels for the hot (log2 N, log2 batch) pairs, when the configured work-group
-// size matches; the general kernel otherwise.  STMT names LN and LB.
+// size matches; the general kernel otherwise.  L2N is the length code: log2 N for a power of two,
+// -1 for N = 3 2^l.  STMT names LN and LB.
 #define LAM_CT_CASE(T_, L2N, L2B, THR, ln, lb, STMT)                          \
   else if (L2N == ln && L2B == lb && THR == ct_threads<T_, ln, lb>()) {      \
     constexpr int LN = ln, LB = lb;                                          \
@@ -444,6 +454,10 @@ static hipError_t prep(Kern k, size_t lds) {
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 4, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 3, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 11, 3, STMT)                                \
+  else if (L2N < 0) {                                                        \
+    constexpr int LN = -1, LB = 0;                                           \
+    STMT;                                                                    \
+  }                                                                          \
   else {                                                                     \
     constexpr int LN = 0, LB = 0;                                            \
     STMT;                                                                    \
@@ -455,10 +469,20 @@ static hipError_t prep(Kern k, size_t lds) {
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 3, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 2, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 11, 1, STMT)                                \
+  else if (L2N < 0) {                                                        \
+    constexpr int LN = -1, LB = 0;                                           \
+    STMT;                                                                    \
+  }                                                                          \
   else {                                                                     \
     constexpr int LN = 0, LB = 0;                                            \
     STMT;                                                                    \
   }
+
+// length code of a transform of N = 2^l or 3 2^l points (l = its trailing zero bits): l, or -1
+static int len_code(int N) {
+  const int l = __builtin_ctz((unsigned)N);
+  return N == (1 << l) ? l : -1;
+}
 
 template <typename Kern, typename... Args>
 static hipError_t launch(Kern k, dim3 grid, int threads, size_t lds, hipStream_t s, Args... args) {
@@ -472,21 +496,26 @@ template <typename T>
 hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* u1, int y0, int ny, size_t in_zs,
                        const Dims& D, const Tables<T>& tb, hipStream_t s) {
   const dim3 grid(D.n2 >> c.z_log2TX, ny);
+  const int code = len_code(D.M0);
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
     if constexpr (MH == 4) {
       if (real_in) {
-        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+        LAM_CT_COLS(T, code, c.z_log2TX, c.z_threads,
                     e = launch(k_zfwd<T, MH, true, LN, LB>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX,
                                y0, in_zs))
       } else {
-        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+        LAM_CT_COLS(T, code, c.z_log2TX, c.z_threads,
                     e = launch(k_zfwd<T, MH, false, LN, LB>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX,
                                y0, in_zs))
       }
     } else {
-      e = real_in ? launch(k_zfwd<T, MH, true>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs)
-                  : launch(k_zfwd<T, MH, false>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
+      if (code < 0)
+        e = real_in ? launch(k_zfwd<T, MH, true, -1>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs)
+                    : launch(k_zfwd<T, MH, false, -1>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
+      else
+        e = real_in ? launch(k_zfwd<T, MH, true>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs)
+                    : launch(k_zfwd<T, MH, false>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
     }
   });
   return e;
@@ -496,21 +525,26 @@ template <typename T>
 hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_out, int y0, int ny, size_t out_zs,
                        const Dims& D, const Tables<T>& tb, hipStream_t s) {
   const dim3 grid(D.n2 >> c.z_log2TX, ny);
+  const int code = len_code(D.M0);
   hipError_t e = hipSuccess;
   LAM_MH_SWITCH(D.m, {
     if constexpr (MH == 4) {
       if (real_out) {
-        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+        LAM_CT_COLS(T, code, c.z_log2TX, c.z_threads,
                     e = launch(k_zadj<T, MH, true, LN, LB>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX,
                                y0, out_zs))
       } else {
-        LAM_CT_COLS(T, D.log2M0, c.z_log2TX, c.z_threads,
+        LAM_CT_COLS(T, code, c.z_log2TX, c.z_threads,
                     e = launch(k_zadj<T, MH, false, LN, LB>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX,
                                y0, out_zs))
       }
     } else {
-      e = real_out ? launch(k_zadj<T, MH, true>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs)
-                   : launch(k_zadj<T, MH, false>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
+      if (code < 0)
+        e = real_out ? launch(k_zadj<T, MH, true, -1>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs)
+                     : launch(k_zadj<T, MH, false, -1>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
+      else
+        e = real_out ? launch(k_zadj<T, MH, true>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs)
+                     : launch(k_zadj<T, MH, false>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
     }
   });
   return e;
@@ -521,7 +555,7 @@ hipError_t launch_ycol_fwd(const LaunchCfg& c, const cpx<T>* u1, cpx<T>* Tb, int
                            const Tables<T>& tb, hipStream_t s) {
   const dim3 grid(D.n2 >> c.y_log2TX, ns);
   hipError_t e = hipSuccess;
-  LAM_CT_COLS(T, D.log2M1, c.y_log2TX, c.y_threads,
+  LAM_CT_COLS(T, len_code(D.M1), c.y_log2TX, c.y_threads,
               e = launch(k_ycol_fwd<T, LN, LB>, grid, c.y_threads, c.y_lds, s, u1, Tb, k0, D, tb, c.y_log2TX))
   return e;
 }
@@ -529,9 +563,9 @@ hipError_t launch_ycol_fwd(const LaunchCfg& c, const cpx<T>* u1, cpx<T>* Tb, int
 template <typename T>
 hipError_t launch_xrow_fwd(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* Gb, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s) {
-  const dim3 grid((unsigned)(((size_t)ns << D.log2M1) >> c.x_log2RB));
+  const dim3 grid((unsigned)(((size_t)ns * D.M1) >> c.x_log2RB));
   hipError_t e = hipSuccess;
-  LAM_CT_ROWS(T, D.log2M2, c.x_log2RB, c.x_threads,
+  LAM_CT_ROWS(T, len_code(D.M2), c.x_log2RB, c.x_threads,
               e = launch(k_xrow_fwd<T, LN, LB>, grid, c.x_threads, c.x_lds, s, Tb, Gb, D, tb, c.x_log2RB))
   return e;
 }
@@ -539,9 +573,9 @@ hipError_t launch_xrow_fwd(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* Gb, int
 template <typename T>
 hipError_t launch_xrow_adj(const LaunchCfg& c, const cpx<T>* Gb, cpx<T>* Tb, int ns, const Dims& D,
                            const Tables<T>& tb, hipStream_t s) {
-  const dim3 grid((unsigned)(((size_t)ns << D.log2M1) >> c.x_log2RB));
+  const dim3 grid((unsigned)(((size_t)ns * D.M1) >> c.x_log2RB));
   hipError_t e = hipSuccess;
-  LAM_CT_ROWS(T, D.log2M2, c.x_log2RB, c.x_threads,
+  LAM_CT_ROWS(T, len_code(D.M2), c.x_log2RB, c.x_threads,
               e = launch(k_xrow_adj<T, LN, LB>, grid, c.x_threads, c.x_lds, s, Gb, Tb, D, tb, c.x_log2RB))
   return e;
 }
@@ -551,7 +585,7 @@ hipError_t launch_ycol_adj(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* u1, int
                            const Tables<T>& tb, hipStream_t s) {
   const dim3 grid(D.n2 >> c.y_log2TX, ns);
   hipError_t e = hipSuccess;
-  LAM_CT_COLS(T, D.log2M1, c.y_log2TX, c.y_threads,
+  LAM_CT_COLS(T, len_code(D.M1), c.y_log2TX, c.y_threads,
               e = launch(k_ycol_adj<T, LN, LB>, grid, c.y_threads, c.y_lds, s, Tb, u1, k0, D, tb, c.y_log2TX))
   return e;
 }
@@ -559,26 +593,25 @@ hipError_t launch_ycol_adj(const LaunchCfg& c, const cpx<T>* Tb, cpx<T>* u1, int
 template <typename T>
 hipError_t launch_rowfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, int nproj, const Dims& D,
                          const Tables<T>& tb, hipStream_t s) {
-  const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
+  const int lw = __builtin_ctz((unsigned)D.w);
   const dim3 grid((unsigned)(((size_t)nproj * D.h) >> c.r_log2RB));
   const int inv = inverse ? 1 : 0;
   hipError_t e = hipSuccess;
-  LAM_CT_ROWS(T, log2w, c.r_log2RB, c.r_threads,
-              e = launch(k_rowfft<T, LN, LB>, grid, c.r_threads, c.r_lds, s, in, out, log2w, log2h, c.r_log2RB, inv,
-                         tb))
+  LAM_CT_ROWS(T, len_code(D.w), c.r_log2RB, c.r_threads,
+              e = launch(k_rowfft<T, LN, LB>, grid, c.r_threads, c.r_lds, s, in, out, D.w, lw, c.r_log2RB, inv, tb))
   return e;
 }
 
 template <typename T>
 hipError_t launch_colfft(const LaunchCfg& c, const cpx<T>* in, cpx<T>* out, bool inverse, double scale_d, int nproj,
                          const Dims& D, const Tables<T>& tb, hipStream_t s) {
-  const int log2h = __builtin_ctz(D.h), log2w = __builtin_ctz(D.w);
+  const int lh = __builtin_ctz((unsigned)D.h);
   const dim3 grid(D.w >> c.c_log2TX, nproj);
   const T scale = (T)scale_d;
   const int inv = inverse ? 1 : 0;
   hipError_t e = hipSuccess;
-  LAM_CT_COLS(T, log2h, c.c_log2TX, c.c_threads,
-              e = launch(k_colfft<T, LN, LB>, grid, c.c_threads, c.c_lds, s, in, out, log2h, log2w, c.c_log2TX, inv,
+  LAM_CT_COLS(T, len_code(D.h), c.c_log2TX, c.c_threads,
+              e = launch(k_colfft<T, LN, LB>, grid, c.c_threads, c.c_lds, s, in, out, D.h, lh, D.w, c.c_log2TX, inv,
                          scale, tb))
   return e;
 }

@@ -70,7 +70,13 @@ __host__ __device__ inline int border_class(int o, int TS, int MH) {
 __host__ __device__ inline int band_intervals(const Dims& D, const double* ln, int k, int Y0, int log2TS, int* lo,
                                               int* hi) {
   const double kv = (double)(k - D.h / 2) * D.xy.inv_h;
-  return axis_intervals(ln[3], ln[4], ln[5] * kv, Y0, 1 << log2TS, 1 << D.log2M1, -D.w / 2, D.w / 2 - 1, lo, hi);
+  return axis_intervals(ln[3], ln[4], ln[5] * kv, Y0, 1 << log2TS, D.M1, -D.w / 2, D.w / 2 - 1, lo, hi);
+}
+
+// v modulo M in [0, M), for any sign of v
+__host__ __device__ inline int pmod(int v, int M) {
+  const int r = v % M;
+  return r < 0 ? r + M : r;
 }
 
 // Exact test of one candidate (array indices k, aku; angle cos/sin ct, st): true
@@ -78,11 +84,11 @@ __host__ __device__ inline int band_intervals(const Dims& D, const double* ln, i
 // its border class (3 x row class + column class).
 __host__ __device__ inline bool classify_target(const Dims& D, double ct, double st, int k, int aku, int Y0,
                                                 int log2TS, int MH, int& tx, int& c) {
-  const int TS = 1 << log2TS, M1 = 1 << D.log2M1, M2 = 1 << D.log2M2;
+  const int TS = 1 << log2TS;
   double sx, sy;
   target_coords(D.xy, ct, st, k, aku, sx, sy);
-  const int oy = ((int)floor(sy) - Y0) & (M1 - 1);
-  const int fx = (int)floor(sx) & (M2 - 1);
+  const int oy = pmod((int)floor(sy) - Y0, D.M1);
+  const int fx = pmod((int)floor(sx), D.M2);
   tx = fx >> log2TS;
   c = border_class(oy, TS, MH) * 3 + border_class(fx & (TS - 1), TS, MH);
   return oy < TS;

@@ -254,6 +254,9 @@ int memo_check(lam_plan p, const lam_memo* m, bool state) {
   if (!m) return set_error(LAM_ERR_ARG, "null memoization state");
   if (state && (!m->work || !m->counters)) return set_error(LAM_ERR_ARG, "null memoization work or counters");
   const lam_params& q = plan_params(p);
+  // the chunk views index with shifts
+  for (int v : {q.n0, q.n1, q.n2, q.h, q.w})
+    if (!pow2_in(v, 1, 1 << 30)) return set_error(LAM_ERR_ARG, "memoization needs power-of-two n0, n1, n2, h, w");
   if (!pow2_in(m->chunk_y, 1, q.n1)) return set_error(LAM_ERR_ARG, "chunk_y must be a power of two in [1, n1]");
   if (!pow2_in(m->chunk_kv, 1, q.h)) return set_error(LAM_ERR_ARG, "chunk_kv must be a power of two in [1, h]");
   if (!pow2_in(m->key_dim, 64, 4096)) return set_error(LAM_ERR_ARG, "key_dim must be a power of two in [64, 4096]");

@@ -30,10 +30,12 @@ int ilog2(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
 
 int run(const Geo& g, const char* name) {
   const int R = 2, M1 = R * g.n1, M2 = R * g.n2, nt = (int)g.theta.size();
-  const int TS = std::min(64, std::min(M1, M2)), log2TS = ilog2(TS), ntx = M2 / TS, nty = M1 / TS;
+  int TS = 64;
+  while (M1 % TS || M2 % TS) TS >>= 1;   // the plan's tile: the largest power of two <= 64 dividing both
+  const int log2TS = ilog2(TS), ntx = M2 / TS, nty = M1 / TS;
   Dims D{};
   D.n1 = g.n1; D.n2 = g.n2; D.h = g.h; D.w = g.w; D.ntheta = nt; D.m = g.m;
-  D.log2M1 = ilog2(M1); D.log2M2 = ilog2(M2);
+  D.M1 = M1; D.M2 = M2;
   D.xy.Rn2 = (double)R * g.n2; D.xy.Rn1 = (double)R * g.n1;
   D.xy.inv_w = 1.0 / g.w; D.xy.inv_h = 1.0 / g.h; D.xy.sphi = std::sin(g.phi);
   D.xy.w = g.w; D.xy.h = g.h;
@@ -62,7 +64,8 @@ int run(const Geo& g, const char* name) {
             // the direct classification of the same target
             double sx, sy;
             target_coords(D.xy, cth[t], sth[t], k, aku, sx, sy);
-            const int by = (int)std::floor(sy) & (M1 - 1), bx = (int)std::floor(sx) & (M2 - 1);
+            const int by = (int)(std::floor(sy) - M1 * std::floor(std::floor(sy) / M1));
+            const int bx = (int)(std::floor(sx) - M2 * std::floor(std::floor(sx) / M2));
             const int oy = by % TS, ox = bx % TS;
             const int cy = oy < g.m - 1 ? 0 : (oy >= TS - g.m ? 2 : 1), cx = ox < g.m - 1 ? 0 : (ox >= TS - g.m ? 2 : 1);
             if (by / TS != ty || bx / TS != tx || c != 3 * cy + cx || tx >= ntx) {
@@ -108,5 +111,9 @@ int main() {
   rc |= run({256, 64, 32, 64, 4, 60 * deg, uniform(97)}, "97 angles, rectangular grid");
   rc |= run({128, 128, 32, 128, 8, 30 * deg, edge}, "m = 8");
   rc |= run({128, 64, 32, 64, 1, 30 * deg, uniform(41)}, "m = 1");
+  // grids of 3 2^k points: tiles of 16 (M = 48) and 32 (M1 = 96 beside M2 = 192)
+  rc |= run({24, 24, 24, 24, 4, 20 * deg, edge}, "3 2^k: 48 x 48 grid, edge angles");
+  rc |= run({48, 96, 48, 96, 4, 30 * deg, uniform(61)}, "3 2^k: 96 x 192 grid, 61 angles");
+  rc |= run({96, 64, 24, 128, 4, 35 * deg, edge}, "3 2^k rows beside 2^k columns, wide detector");
   return rc;
 }

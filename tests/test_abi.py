@@ -44,7 +44,8 @@ def test_struct_layout_matches_header():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n0=24), dict(n1=8), dict(n2=8192), dict(h=48), dict(w=0), dict(ntheta=0), dict(phi=math.pi / 2),
+    dict(n0=40), dict(n1=8), dict(n1=12), dict(n2=8192), dict(n2=6144), dict(h=80), dict(h=7), dict(w=0),
+    dict(ntheta=0), dict(phi=math.pi / 2),
     dict(phi=-0.1), dict(phi=float("nan")), dict(oversample=3), dict(m=0), dict(m=9), dict(dtype=2), dict(slab=-1),
 ])
 def test_init_rejects_bad_parameters(bad):
@@ -53,6 +54,16 @@ def test_init_rejects_bad_parameters(bad):
     assert rc == 1
     assert h.value is None
     assert L.lib().lam_last_error().decode()
+
+
+def test_init_accepts_3pow2_sizes():
+    # every length 2^k or 3 2^k in [16, 4096]; the transforms of 3 2^k points take a radix-3 stage
+    lib = L.lib()
+    h = c_void_p()
+    assert lib.lam_init(byref(h), byref(_params(n0=24, n1=48, n2=96, h=1536, w=3072))) == 0, \
+        lib.lam_last_error().decode()
+    assert lib.lam_workspace_bytes(h) > 0
+    lib.lam_destroy(h)
 
 
 def test_init_rejects_nonfinite_theta():

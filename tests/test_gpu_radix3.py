@@ -1,0 +1,186 @@
+"""GPU parity on sizes 3 2^k: the 1.5K^3 family of the paper's evaluation (Section 6.1
+lists 1K^3 and 1.5K^3 inputs; a 1536^3 volume oversamples to grids of 3072 = 3 2^10).
+
+Every transform of 3 2^l points takes the mixed-radix LDS FFT (a radix-3 stage, then
+radix 8/4/2) and every periodic index of such a grid takes compares instead of masks;
+the tile kernels run their general-period instantiation whenever either grid period
+is not a power of two.  The cases mix both families on one plan (a power-of-two axis
+beside a 3 2^k one, a power-of-two detector beside a 3 2^k volume) and reach the 64 x 64
+tile kernels (grids of 192 = 3 tiles).  Bars as for the power-of-two sizes: complex128
+<= 1e-12 and complex64 <= 1e-4 relative L2 against the FP64 oracle, which is pinned to
+the direct NDFT and to the closed-form blob projection at 3 2^k sizes on the CPU.
+
+At 1536^3 (96 angles, 1536^2 detector: the real grids and transform lengths, fewer
+angles so that the oracle's frequency tables fit) the oracle evaluates sampled
+outputs: L^ u of a volume that is non-zero on four y rows only, on three k_v slices,
+and L^* r of data that is non-zero on two k_v slices, on four y rows.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lam_oracle as O
+from paper_2511_01893_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex64: 1e-4, torch.complex128: 1e-12}
+DTYPES = [torch.complex64, torch.complex128]
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_01893_amd import lam
+    lam.lib()
+    return lam
+
+
+def gpu(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def report(name, err, tol):
+    print(f"{name}: rel err {err:.3e} (bar {tol:.0e})", flush=True)
+    assert err <= tol, (name, err, tol)
+
+
+def rel(a, b):
+    return ((a - b).norm() / b.norm()).item()
+
+
+def vdot(x, y, chunk=128):
+    """<x, y> in FP64 over chunks of the first axis (torch.vdot takes at most 2^31 elements)."""
+    s = 0.0
+    for i in range(0, x.shape[0], chunk):
+        xs, ys = x[i:i + chunk].to(torch.complex128), y[i:i + chunk].to(torch.complex128)
+        s = s + torch.vdot(xs.reshape(-1), ys.reshape(-1)).item()
+    return s
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+def test_all_entry_points_48(L, dtype):
+    n, nt, phi = 48, 19, math.radians(20.0)
+    plan = L.Plan(n, ntheta=nt, phi=phi, h=n, w=n, dtype=dtype)
+    geo = O.Geometry(n, n, n, nt, phi, n, n, 2, 4)
+    u = I.blob_phantom(geo.vol_shape, I.draw_blobs(11, 8)).astype(np.complex128)
+    d = I.random_detector_data(geo.data_shape, 11)
+    tol = TOL[dtype]
+    ug, dg = gpu(u, dtype), gpu(d, dtype)
+    report("fwd", O.relerr(host(plan.fwd(ug)), O.lam_fwd(u, geo)), tol)
+    report("adj", O.relerr(host(plan.adj(dg)), O.lam_adj(d, geo)), tol)
+    dhat = O.f2d_unnorm(d)
+    report("data_hat", O.relerr(host(plan.data_hat(dg)), dhat), 1e-5 if dtype == torch.complex64 else 1e-12)
+    report("fwd_hat", O.relerr(host(plan.fwd_hat(ug)), O.lam_fwd_hat(u, geo)), tol)
+    report("fwd_hat-dhat", O.relerr(host(plan.fwd_hat(ug, gpu(dhat, dtype))), O.lam_fwd_hat(u, geo, dhat)), tol)
+    report("adj_hat", O.relerr(host(plan.adj_hat(gpu(dhat, dtype))), O.lam_adj_hat(dhat, geo)), tol)
+    ur = u.real.copy()
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    report("fwd_real", O.relerr(host(plan.fwd(torch.from_numpy(ur).to(rdt).cuda())), O.lam_fwd(ur, geo)), tol)
+    report("adj_real", O.relerr(host(plan.adj(dg, real=True)), O.lam_adj(d, geo).real), tol)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("case", [
+    dict(n0=24, n1=48, n2=96, ntheta=7, phi=35.0, h=48, w=24),            # every size different, all 3 2^k
+    dict(n0=32, n1=48, n2=64, ntheta=11, phi=20.0, h=24, w=64),           # 3 2^k beside 2^k on one plan
+    dict(n0=24, n1=96, n2=96, ntheta=13, phi=30.0, h=48, w=96),           # 192 x 192 grid: 3 x 3 tiles of 64
+    dict(n0=16, n1=64, n2=96, ntheta=9, phi=25.0, h=16, w=96),            # 128 x 192 grid: 2 x 3 tiles
+    dict(n0=24, n1=48, n2=48, ntheta=9, phi=50.0, h=24, w=48, m=8),
+    dict(n0=24, n1=96, n2=96, ntheta=7, phi=40.0, h=24, w=96, m=3),       # 8-lane groups on 64 x 64 tiles
+    dict(n0=24, n1=48, n2=48, ntheta=9, phi=25.0, h=48, w=48, slab=5),    # ragged last slab
+    dict(n0=48, n1=48, n2=48, ntheta=5, phi=0.0, h=48, w=48),             # tomography (integer coordinates)
+], ids=["rect", "mixed", "tiles3x3", "tiles2x3", "m8", "m3-tiles", "slab5", "phi0"])
+def test_geometries_3pow2(L, dtype, case):
+    c = dict(case)
+    m, slab = c.pop("m", 4), c.pop("slab", 0)
+    phi = math.radians(c["phi"])
+    theta = [0.0, math.pi / 2, math.pi, 1.25 * math.pi, 0.3] if c["phi"] == 0.0 else None
+    plan = L.Plan(c["n0"], c["n1"], c["n2"], ntheta=c["ntheta"], phi=phi, h=c["h"], w=c["w"], m=m, dtype=dtype,
+                  slab=slab, theta=theta)
+    geo = O.Geometry(c["n0"], c["n1"], c["n2"], c["ntheta"], phi, c["h"], c["w"], 2, m, theta=theta)
+    u = I.random_complex(geo.vol_shape, 17)
+    d = I.random_detector_data(geo.data_shape, 17)
+    tol = TOL[dtype]
+    report("fwd", O.relerr(host(plan.fwd(gpu(u, dtype))), O.lam_fwd(u, geo)), tol)
+    report("adj", O.relerr(host(plan.adj(gpu(d, dtype))), O.lam_adj(d, geo)), tol)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("case", [
+    dict(n0=1536, n1=24, n2=24, ntheta=4, phi=25.0, h=48, w=24),          # z transforms of 3072 points
+    dict(n0=24, n1=1536, n2=24, ntheta=3, phi=30.0, h=24, w=48),          # y transforms of 3072 points
+    dict(n0=24, n1=24, n2=1536, ntheta=3, phi=30.0, h=24, w=48),          # x transforms of 3072 points
+    dict(n0=24, n1=24, n2=24, ntheta=2, phi=20.0, h=1536, w=1536),        # 2D DFT of 1536^2
+], ids=["z3072", "y3072", "x3072", "dft1536"])
+def test_long_transforms_3pow2(L, dtype, case):
+    c = dict(case)
+    phi = math.radians(c["phi"])
+    plan = L.Plan(c["n0"], c["n1"], c["n2"], ntheta=c["ntheta"], phi=phi, h=c["h"], w=c["w"], dtype=dtype)
+    g = O.Geometry(c["n0"], c["n1"], c["n2"], c["ntheta"], phi, c["h"], c["w"], 2, 4)
+    u = I.random_complex(g.vol_shape, 43)
+    d = I.random_detector_data(g.data_shape, 43)
+    tol = TOL[dtype]
+    report("fwd", O.relerr(host(plan.fwd(gpu(u, dtype))), O.lam_fwd(u, g)), tol)
+    report("adj", O.relerr(host(plan.adj(gpu(d, dtype))), O.lam_adj(d, g)), tol)
+    report("data_hat", O.relerr(host(plan.data_hat(gpu(d, dtype))), O.f2d_unnorm(d)),
+           1e-5 if dtype == torch.complex64 else 1e-12)
+
+
+def test_lam1536_sampled_96_angles(L):
+    """1536^3, 1536^2 detector, 96 angles, 20 deg, complex64: sampled outputs against the oracle,
+    the adjoint identity on a blob phantom, and complex64 against complex128 on the whole arrays."""
+    n, nt, phi = 1536, 96, math.radians(20.0)
+    plan = L.Plan(n, ntheta=nt, phi=phi, h=n, w=n, dtype=torch.complex64)
+    geo = O.Geometry(n, n, n, nt, phi, n, n, 2, 4)
+    rows, kvs = [5, 700, 768, 1500], [0, 613, 1100]
+    sub = O.Geometry(n, len(rows), n, nt, phi, n, n, 2, 4)   # the z steps act on each (y, x) column alone
+    nu_x, nu_y, _ = O.frequencies(geo)
+    # L^ u of a volume that is non-zero on four rows: F_u1D of those rows, F_u2D of three slices
+    vals = host(gpu(I.random_complex((n, len(rows), n), 61), torch.complex64))
+    u = torch.zeros((n, n, n), dtype=torch.complex64, device="cuda")
+    u[:, rows, :] = gpu(vals, torch.complex64)
+    got = host(plan.fwd_hat(u)[:, kvs, :])
+    del u
+    u1 = O.fu1d(vals, sub)
+    ref = np.empty((nt, len(kvs), n), dtype=np.complex128)
+    for i, kv in enumerate(kvs):
+        plane = np.zeros((n, n), dtype=np.complex128)
+        plane[rows] = u1[kv]
+        ref[:, i, :] = O.usfft2d_fwd(plane, n * nu_x[:, kv, :], n * nu_y[:, kv, :], 2, 4)
+    report(f"1536^3 L^ u on slices {kvs}", O.relerr(got, ref), 1e-4)
+    # L^* r of data that is non-zero on two slices, on the four rows
+    kv2 = [37, 1201]
+    rv = host(gpu(I.random_complex((nt, len(kv2), n), 62), torch.complex64))
+    r = torch.zeros((nt, n, n), dtype=torch.complex64, device="cuda")
+    r[:, kv2, :] = gpu(rv, torch.complex64)
+    got = host(plan.adj_hat(r)[:, rows, :])
+    del r
+    u1 = np.zeros((n, len(rows), n), dtype=np.complex128)
+    for i, kv in enumerate(kv2):
+        u1[kv] = O.usfft2d_adj(rv[:, i, :], n * nu_x[:, kv, :], n * nu_y[:, kv, :], n, n, 2, 4)[rows]
+    report(f"1536^3 L^* r (r on slices {kv2}) on rows {rows}", O.relerr(got, O.fu1d_adj(u1, sub)), 1e-4)
+    del nu_x, nu_y, u1
+    # whole-array properties on a blob phantom
+    ub = I.blob_phantom_torch((n, n, n), I.draw_blobs(6, 64), "cuda", torch.float32)
+    d = I.random_complex_torch(plan.data_shape, 206, "cuda", torch.complex64)
+    Lu, Lsd = plan.fwd(ub), plan.adj(d, real=True)
+    # u real and Lsd = Re L* d: Re <d, L u> = <Re L* d, u>
+    a, b = vdot(d, Lu), vdot(Lsd, ub)
+    err = abs(a.real - b.real) / (Lu.to(torch.complex128).norm() * d.to(torch.complex128).norm()).item()
+    print(f"1536^3 adjoint identity {err:.2e}", flush=True)
+    assert err < 1e-5
+    del plan
+    torch.cuda.empty_cache()
+    p128 = L.Plan(n, ntheta=nt, phi=phi, h=n, w=n, dtype=torch.complex128)
+    e_f = rel(Lu.to(torch.complex128), p128.fwd(ub.double()))
+    e_a = rel(Lsd.double(), p128.adj(d.to(torch.complex128), real=True))
+    print(f"1536^3 c64 vs c128: fwd {e_f:.2e} adj {e_a:.2e}", flush=True)
+    assert e_f < 1e-4 and e_a < 1e-4

@@ -22,4 +22,4 @@ def test_list_enumeration_edge_geometries():
     r = subprocess.run([out], capture_output=True, text=True, timeout=120)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count("each listed once") == 7
+    assert r.stdout.count("each listed once") == 10

@@ -79,6 +79,17 @@ def test_operator_matches_ndft_rectangular():
     assert O.relerr(O.lam_adj(d, g), O.ndft_adj(d, g)) < 1e-7
 
 
+@pytest.mark.parametrize("m,tol", [(4, 3e-4), (8, 1e-7)])
+def test_operator_matches_ndft_3pow2(m, tol):
+    # sizes 3 2^k (the 1.5K^3 family, oversampled grids 3 2^(k+1)), beside a 2^k axis and detector side
+    g = O.Geometry(12, 24, 16, 7, 25 * DEG, 24, 12, 2, m)
+    u = I.random_complex(g.vol_shape, 5)
+    assert O.relerr(O.fu1d(u, g), O.ndft_fu1d(u, g)) < tol
+    assert O.relerr(O.lam_fwd(u, g), O.ndft_fwd(u, g)) < tol
+    d = I.random_detector_data(g.data_shape, 5)
+    assert O.relerr(O.lam_adj(d, g), O.ndft_adj(d, g)) < tol
+
+
 def test_ndft_definition_by_brute_force():
     # the separable NDFT equals the triple sum over voxels written out element by element
     g = O.Geometry(4, 4, 4, 3, 30 * DEG, 4, 4, 2, 4)
@@ -125,6 +136,15 @@ def test_blob_closed_form_projection(m, tol):
     d = O.lam_fwd(u, g)
     assert O.relerr(d, ref) < tol
     assert O.relerr(O.ndft_fwd(u, g), ref) < 1e-8
+
+
+def test_blob_closed_form_3pow2():
+    # a 48^3 volume and 48^2 detector (3 2^4; oversampled grids of 96): the 1.5K^3 shape scaled down
+    N = 48
+    g = O.Geometry(N, N, N, 9, 20 * DEG, N, N, 2, 4)
+    c, s, A = np.array([0.04, 0.06, -0.07]), 0.06, 0.9
+    u = I.blob_phantom(g.vol_shape, I.BlobSet(c[None], np.array([s]), np.array([A]), None))
+    assert O.relerr(O.lam_fwd(u, g), _blob_projection(g, c, s, A, N)) < 2e-4
 
 
 def test_blob_closed_form_non_cubic_detector():
