@@ -446,7 +446,7 @@ def main():
            "note": "78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz, packed FP32 disabled; 157.3 with packing"}
 
     result = {
-        "metric": "lam fwd+adj pairs/s at 512^3 (c64 vs FP64, rel err <=1e-4); % HBM roofline",
+        "metric": f"lam fwd+adj pairs/s at {n}^3 (c64 vs FP64, rel err <=1e-4); % HBM roofline",
         "value": 1000.0 / ms,
         "unit": "pairs/s",
         "n_gpus": 1,

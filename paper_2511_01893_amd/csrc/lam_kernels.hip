@@ -23,6 +23,19 @@ extern __shared__ __align__(16) unsigned char lam_smem[];
 
 __device__ __forceinline__ int sgn_parity(int k) { return (k & 1) ? -1 : 1; }
 
+// Block (bx, by) of a 2D grid of column blocks, in an XCD-aware order.  The dispatcher deals
+// work-groups to the 8 XCDs round robin by linear id, and each XCD has its own L2; neighbouring
+// x-tiles of a column kernel read neighbouring pieces of the same HBM lines (a tile row is TX
+// values, 16 to 128 bytes).  So each XCD is given a contiguous run of the logical blocks: logical id
+// (lin mod 8) (total / 8) + lin / 8 for linear id lin (the last total mod 8 keep theirs).
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+  const int gx = gridDim.x, total = gx * gridDim.y, lin = blockIdx.x + blockIdx.y * gx;
+  const int per = total >> 3;
+  const int l = lin < per * 8 ? (lin & 7) * per + (lin >> 3) : lin;
+  by = l / gx;
+  bx = l - by * gx;
+}
+
 // The FFT kernels take template sizes LN (log2 of the transform length) and LB (log2 of the
 // transforms per block): LN = 0 selects the general kernel for power-of-two lengths (sizes from the
 // arguments), LN = -1 the general kernel for lengths 3 2^l (the mixed-radix LDS FFT); otherwise the
@@ -59,8 +72,10 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   constexpr bool P2 = LN >= 0;
   const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? LN : D.lM0;
   const int TX = 1 << log2TX, M0 = LN > 0 ? 1 << LN : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
-  // blockIdx.y is the row within the input slab; y the row of the volume
-  const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
+  // block row yl is the row within the input slab; y the row of the volume
+  int bx, yl;
+  xcd_block(bx, yl);
+  const int x0 = bx * TX, y = y0 + yl;
   if (D.skip.skip(y)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const size_t plane = (size_t)D.n1 * D.n2;
@@ -128,8 +143,10 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
   constexpr bool P2 = LN >= 0;
   const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? LN : D.lM0;
   const int TX = 1 << log2TX, M0 = LN > 0 ? 1 << LN : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
-  // blockIdx.y is the row within the output slab; y the row of the volume
-  const int x0 = blockIdx.x * TX, yl = blockIdx.y, y = y0 + yl;
+  // block row yl is the row within the output slab; y the row of the volume
+  int bx, yl;
+  xcd_block(bx, yl);
+  const int x0 = bx * TX, y = y0 + yl;
   if (D.skip.skip(y)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const size_t plane = (size_t)D.n1 * D.n2;
@@ -212,7 +229,9 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
   constexpr bool P2 = LN >= 0;
   const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? LN : D.lM1;
   const int TX = 1 << log2TX, M1 = LN > 0 ? 1 << LN : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
-  const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
+  int bx, kk;
+  xcd_block(bx, kk);
+  const int x0 = bx * TX, k = k0 + kk;
   if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
@@ -250,7 +269,9 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
   constexpr bool P2 = LN >= 0;
   const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? LN : D.lM1;
   const int TX = 1 << log2TX, M1 = LN > 0 ? 1 << LN : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
-  const int x0 = blockIdx.x * TX, kk = blockIdx.y, k = k0 + kk;
+  int bx, kk;
+  xcd_block(bx, kk);
+  const int x0 = bx * TX, k = k0 + kk;
   if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
@@ -390,8 +411,10 @@ __global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, 
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
   const int log2TX = LN > 0 ? LB : log2TX_, lH = LN > 0 ? LN : lH_;
   const int TX = 1 << log2TX, H = LN > 0 ? 1 << LN : H_;
-  const int p0 = blockIdx.x * TX;
-  const size_t base = (size_t)blockIdx.y * H * W;
+  int bx, by;
+  xcd_block(bx, by);
+  const int p0 = bx * TX;
+  const size_t base = (size_t)by * H * W;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
     cpx<T> w[vpt<T>()];

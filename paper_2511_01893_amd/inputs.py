@@ -143,4 +143,6 @@ WORKLOADS = {
     "lam512": dict(n=512, ntheta=512, phi_deg=30.0, det=512, nblobs=64, cubes=True, seed=3),
     "lam1024": dict(n=1024, ntheta=1024, phi_deg=20.0, det=1024, nblobs=256, cubes=False, seed=4),
     "lam2048": dict(n=2048, ntheta=2048, phi_deg=20.0, det=2048, nblobs=1024, cubes=False, seed=5),
+    # the paper's 1.5K^3 shape (Section 6.1): transforms of 3 2^k points
+    "lam1536": dict(n=1536, ntheta=1536, phi_deg=20.0, det=1536, nblobs=512, cubes=False, seed=6),
 }
