@@ -262,6 +262,83 @@ __device__ __forceinline__ void lds_fft3(cpx<T>* buf, int a, int log2nb, int sp,
   }
 }
 
+// The 3 2^A-point FFT with A, the batch NB = 2^LOG2NB and the layout fixed at compile time (the
+// hot sizes of the 3 2^k grids): every division by 3 2^s is by a constant, the stages unroll, and
+// the work-group size is the launch's, max(64, N NB / VPT rounded up to whole waves).  COLS as for
+// lds_fft_ct.
+template <int VPT, int A, int LOG2NB> constexpr int fft3_threads() {
+  return ((3 << (A + LOG2NB)) + 64 * VPT - 1) / (64 * VPT) * 64 < 64
+             ? 64
+             : ((3 << (A + LOG2NB)) + 64 * VPT - 1) / (64 * VPT) * 64;
+}
+
+template <typename T, int R, int VPT, bool PAD, int A, int LOG2NB, bool COLS, int LS>
+__device__ __forceinline__ void fft_stage3_ct(cpx<T>* buf, const cpx<T>* __restrict__ tw3, int log2tw3) {
+  constexpr int LR = R == 3 ? 0 : (R == 8 ? 3 : (R == 4 ? 2 : 1));
+  constexpr int N = 3 << A;
+  constexpr int NBF = R == 3 ? (1 << A) : (3 << (A - LR));   // butterflies per transform
+  constexpr int TOTAL = NBF << LOG2NB;
+  constexpr int NTH = fft3_threads<VPT, A, LOG2NB>();
+  constexpr int IT = (TOTAL + NTH - 1) / NTH;
+  constexpr int NS = R == 3 ? 1 : 3 << LS;                   // values combined by earlier stages
+  auto at = [](int p, int b) { return lpad<PAD>(COLS ? (p << LOG2NB) + b : b * N + p); };
+  auto map = [](int t, int& j, int& b) {
+    if (COLS) { b = t & ((1 << LOG2NB) - 1); j = t >> LOG2NB; }
+    else { b = (int)((unsigned)t / (unsigned)NBF); j = t - b * NBF; }
+  };
+  const int tid = threadIdx.x;
+  cpx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * NTH;
+    if (TOTAL % NTH == 0 || t < TOTAL) {
+      int j, b;
+      map(t, j, b);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = buf[at(j + r * NBF, b)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int t = tid + it * NTH;
+    if (TOTAL % NTH == 0 || t < TOTAL) {
+      int j, b;
+      map(t, j, b);
+      int idxD;
+      if constexpr (R == 3) {
+        dft3(v[it]);
+        idxD = 3 * j;
+      } else {
+        const int hi = (int)((unsigned)j / (unsigned)NS), k = j - hi * NS;
+        twiddle_dft<T, R>(v[it], tw3, k, log2tw3 - LS - LR);
+        idxD = hi * NS * R + k;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[at(idxD + r * NS, b)] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int VPT, bool PAD, int A, int LOG2NB, bool COLS, int REM, int LS>
+__device__ __forceinline__ void lds_fft3_ct_rest(cpx<T>* buf, const cpx<T>* __restrict__ tw3, int log2tw3) {
+  if constexpr (REM >= 3) {
+    fft_stage3_ct<T, 8, VPT, PAD, A, LOG2NB, COLS, LS>(buf, tw3, log2tw3);
+    lds_fft3_ct_rest<T, VPT, PAD, A, LOG2NB, COLS, REM - 3, LS + 3>(buf, tw3, log2tw3);
+  } else if constexpr (REM == 2) {
+    fft_stage3_ct<T, 4, VPT, PAD, A, LOG2NB, COLS, LS>(buf, tw3, log2tw3);
+  } else if constexpr (REM == 1) {
+    fft_stage3_ct<T, 2, VPT, PAD, A, LOG2NB, COLS, LS>(buf, tw3, log2tw3);
+  }
+}
+
+template <typename T, int VPT, bool PAD, int A, int LOG2NB, bool COLS>
+__device__ __forceinline__ void lds_fft3_ct(cpx<T>* buf, const cpx<T>* __restrict__ tw3, int log2tw3) {
+  fft_stage3_ct<T, 3, VPT, PAD, A, LOG2NB, COLS, 0>(buf, tw3, log2tw3);
+  lds_fft3_ct_rest<T, VPT, PAD, A, LOG2NB, COLS, A, 0>(buf, tw3, log2tw3);
+}
+
 // The same FFT with the transform length N = 2^LOG2N and the batch NB =
 // 2^LOG2NB fixed at compile time (the hot sizes): every index is a shift or a
 // constant, the stage sequence is unrolled and the work-group size is the

@@ -36,12 +36,16 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by) {
   bx = l - by * gx;
 }
 
-// The FFT kernels take template sizes LN (log2 of the transform length) and LB (log2 of the
-// transforms per block): LN = 0 selects the general kernel for power-of-two lengths (sizes from the
-// arguments), LN = -1 the general kernel for lengths 3 2^l (the mixed-radix LDS FFT); otherwise the
-// sizes are compile-time constants (the hot sizes) and the compile-time LDS FFT runs.
+// The FFT kernels take a template length code LN and LB (log2 of the transforms per block):
+// LN = 0 selects the general kernel for power-of-two lengths (sizes from the arguments), LN = -1 the
+// general kernel for lengths 3 2^l (the mixed-radix LDS FFT); otherwise the sizes are compile-time
+// constants (the hot sizes): LN in 1..31 the length 2^LN, LN >= 32 the length 3 2^(LN - 32).
+template <int LN> constexpr bool p2_len() { return LN >= 0 && LN < 32; }
+template <int LN> constexpr int ct_l() { return LN >= 32 ? LN - 32 : LN; }
+template <int LN> constexpr int ct_n() { return LN >= 32 ? 3 << (LN - 32) : 1 << LN; }
 template <typename T, int LN, int LB> constexpr int ct_threads() {
-  return ((1 << (LN + LB)) / vpt<T>()) < 64 ? 64 : ((1 << (LN + LB)) / vpt<T>());
+  return LN >= 32 ? fft3_threads<vpt<T>(), LN - 32, LB>()
+                  : (((1 << (LN + LB)) / vpt<T>()) < 64 ? 64 : ((1 << (LN + LB)) / vpt<T>()));
 }
 template <typename T, int LN, int LB> __device__ __forceinline__ int block_threads() {
   if constexpr (LN > 0) return ct_threads<T, LN, LB>();
@@ -50,14 +54,16 @@ template <typename T, int LN, int LB> __device__ __forceinline__ int block_threa
 // column blocks: element (p, b) at p 2^log2TX + b; the length is 2^lN, or 3 2^lN for LN = -1
 template <typename T, int LN, int LB>
 __device__ __forceinline__ void fft_cols(cpx<T>* buf, int lN, int log2TX, const Tables<T>& tb, int nth) {
-  if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), false, LN, LB, true>(buf, tb.tw, tb.log2tw);
+  if constexpr (LN >= 32) lds_fft3_ct<T, vpt<T>(), false, LN - 32, LB, true>(buf, tb.tw3, tb.log2tw3);
+  else if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), false, LN, LB, true>(buf, tb.tw, tb.log2tw);
   else if constexpr (LN < 0) lds_fft3<T, vpt<T>()>(buf, lN, log2TX, 1 << log2TX, 1, true, tb.tw3, tb.log2tw3, nth);
   else lds_fft<T, vpt<T>()>(buf, lN, log2TX, 1 << log2TX, 1, true, tb.tw, tb.log2tw, nth);
 }
 // row blocks: element (p, b) at b N + p, one pad slot per 8 elements; N = 2^lN, or 3 2^lN for LN = -1
 template <typename T, int LN, int LB>
 __device__ __forceinline__ void fft_rows(cpx<T>* buf, int lN, int N, int log2RB, const Tables<T>& tb, int nth) {
-  if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), true, LN, LB, false>(buf, tb.tw, tb.log2tw);
+  if constexpr (LN >= 32) lds_fft3_ct<T, vpt<T>(), true, LN - 32, LB, false>(buf, tb.tw3, tb.log2tw3);
+  else if constexpr (LN > 0) lds_fft_ct<T, vpt<T>(), true, LN, LB, false>(buf, tb.tw, tb.log2tw);
   else if constexpr (LN < 0) lds_fft3<T, vpt<T>(), true>(buf, lN, log2RB, 1, N, false, tb.tw3, tb.log2tw3, nth);
   else lds_fft<T, vpt<T>(), true>(buf, lN, log2RB, 1, N, false, tb.tw, tb.log2tw, nth);
 }
@@ -69,9 +75,9 @@ template <typename T, int MH, bool REAL_IN, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx<T>* __restrict__ u1, Dims D,
                                                Tables<T> tb, int log2TX_, int y0, size_t in_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  constexpr bool P2 = LN >= 0;
-  const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? LN : D.lM0;
-  const int TX = 1 << log2TX, M0 = LN > 0 ? 1 << LN : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
+  constexpr bool P2 = p2_len<LN>();
+  const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? ct_l<LN>() : D.lM0;
+  const int TX = 1 << log2TX, M0 = LN > 0 ? ct_n<LN>() : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // block row yl is the row within the input slab; y the row of the volume
   int bx, yl;
   xcd_block(bx, yl);
@@ -140,9 +146,9 @@ template <typename T, int MH, bool REAL_OUT, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, void* __restrict__ uout, Dims D,
                                                Tables<T> tb, int log2TX_, int y0, size_t out_zs) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  constexpr bool P2 = LN >= 0;
-  const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? LN : D.lM0;
-  const int TX = 1 << log2TX, M0 = LN > 0 ? 1 << LN : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
+  constexpr bool P2 = p2_len<LN>();
+  const int log2TX = LN > 0 ? LB : log2TX_, lM0 = LN > 0 ? ct_l<LN>() : D.lM0;
+  const int TX = 1 << log2TX, M0 = LN > 0 ? ct_n<LN>() : D.M0, n0 = LN > 0 ? M0 / 2 : D.n0;   // R = 2
   // block row yl is the row within the output slab; y the row of the volume
   int bx, yl;
   xcd_block(bx, yl);
@@ -226,9 +232,9 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1, cpx<T>* __restrict__ Tb, int k0,
                                                    Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  constexpr bool P2 = LN >= 0;
-  const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? LN : D.lM1;
-  const int TX = 1 << log2TX, M1 = LN > 0 ? 1 << LN : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
+  constexpr bool P2 = p2_len<LN>();
+  const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? ct_l<LN>() : D.lM1;
+  const int TX = 1 << log2TX, M1 = LN > 0 ? ct_n<LN>() : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   int bx, kk;
   xcd_block(bx, kk);
   const int x0 = bx * TX, k = k0 + kk;
@@ -266,9 +272,9 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb, cpx<T>* __restrict__ u1, int k0,
                                                    Dims D, Tables<T> tb, int log2TX_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  constexpr bool P2 = LN >= 0;
-  const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? LN : D.lM1;
-  const int TX = 1 << log2TX, M1 = LN > 0 ? 1 << LN : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
+  constexpr bool P2 = p2_len<LN>();
+  const int log2TX = LN > 0 ? LB : log2TX_, lM1 = LN > 0 ? ct_l<LN>() : D.lM1;
+  const int TX = 1 << log2TX, M1 = LN > 0 ? ct_n<LN>() : D.M1, n1 = LN > 0 ? M1 / 2 : D.n1, n2 = D.n2;   // R = 2
   int bx, kk;
   xcd_block(bx, kk);
   const int x0 = bx * TX, k = k0 + kk;
@@ -301,9 +307,9 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb, cpx<T>* __restrict__ Gb, Dims D,
                                                    Tables<T> tb, int log2RB_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  constexpr bool P2 = LN >= 0;
-  const int log2RB = LN > 0 ? LB : log2RB_, lM2 = LN > 0 ? LN : D.lM2;
-  const int RB = 1 << log2RB, M2 = LN > 0 ? 1 << LN : D.M2, n2 = M2 / 2, ln2 = lM2 - 1;
+  constexpr bool P2 = p2_len<LN>();
+  const int log2RB = LN > 0 ? LB : log2RB_, lM2 = LN > 0 ? ct_l<LN>() : D.lM2;
+  const int RB = 1 << log2RB, M2 = LN > 0 ? ct_n<LN>() : D.M2, n2 = M2 / 2, ln2 = lM2 - 1;
   const int r0 = blockIdx.x * RB;   // slab rows: at most h M1 < 2^31
   if (D.skip.hit && D.skip.skip(D.slice_of(r0))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -337,9 +343,9 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb, cpx<T>* __restrict__ Tb, Dims D,
                                                    Tables<T> tb, int log2RB_) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  constexpr bool P2 = LN >= 0;
-  const int log2RB = LN > 0 ? LB : log2RB_, lM2 = LN > 0 ? LN : D.lM2;
-  const int RB = 1 << log2RB, M2 = LN > 0 ? 1 << LN : D.M2, n2 = M2 / 2, ln2 = lM2 - 1;
+  constexpr bool P2 = p2_len<LN>();
+  const int log2RB = LN > 0 ? LB : log2RB_, lM2 = LN > 0 ? ct_l<LN>() : D.lM2;
+  const int RB = 1 << log2RB, M2 = LN > 0 ? ct_n<LN>() : D.M2, n2 = M2 / 2, ln2 = lM2 - 1;
   const int r0 = blockIdx.x * RB;   // slab rows: at most h M1 < 2^31
   if (D.skip.hit && D.skip.skip(D.slice_of(r0))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
@@ -374,10 +380,10 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
 template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, int L_, int lL_, int log2RB_,
                                                  int inverse, Tables<T> tb) {
-  constexpr bool P2 = LN >= 0;
+  constexpr bool P2 = p2_len<LN>();
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2RB = LN > 0 ? LB : log2RB_, lL = LN > 0 ? LN : lL_;
-  const int RB = 1 << log2RB, L = LN > 0 ? 1 << LN : L_;
+  const int log2RB = LN > 0 ? LB : log2RB_, lL = LN > 0 ? ct_l<LN>() : lL_;
+  const int RB = 1 << log2RB, L = LN > 0 ? ct_n<LN>() : L_;
   const size_t r0 = (size_t)blockIdx.x * RB;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   {
@@ -409,8 +415,8 @@ template <typename T, int LN = 0, int LB = 0>
 __global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, int H_, int lH_, int W,
                                                  int log2TX_, int inverse, T scale, Tables<T> tb) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lam_smem);
-  const int log2TX = LN > 0 ? LB : log2TX_, lH = LN > 0 ? LN : lH_;
-  const int TX = 1 << log2TX, H = LN > 0 ? 1 << LN : H_;
+  const int log2TX = LN > 0 ? LB : log2TX_, lH = LN > 0 ? ct_l<LN>() : lH_;
+  const int TX = 1 << log2TX, H = LN > 0 ? ct_n<LN>() : H_;
   int bx, by;
   xcd_block(bx, by);
   const int p0 = bx * TX;
@@ -464,7 +470,7 @@ static hipError_t prep(Kern k, size_t lds) {
 
 // Compile-time-size kernels for the hot (log2 N, log2 batch) pairs, when the configured work-group
 // size matches; the general kernel otherwise.  L2N is the length code: log2 N for a power of two,
-// -1 for N = 3 2^l.  STMT names LN and LB.
+// 32 + l for N = 3 2^l.  STMT names LN and LB.
 #define LAM_CT_CASE(T_, L2N, L2B, THR, ln, lb, STMT)                          \
   else if (L2N == ln && L2B == lb && THR == ct_threads<T_, ln, lb>()) {      \
     constexpr int LN = ln, LB = lb;                                          \
@@ -477,7 +483,11 @@ static hipError_t prep(Kern k, size_t lds) {
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 4, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 3, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 11, 3, STMT)                                \
-  else if (L2N < 0) {                                                        \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 42, 2, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 42, 1, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 41, 3, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 41, 2, STMT)                                \
+  else if (L2N >= 32) {                                                        \
     constexpr int LN = -1, LB = 0;                                           \
     STMT;                                                                    \
   }                                                                          \
@@ -492,7 +502,10 @@ static hipError_t prep(Kern k, size_t lds) {
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 3, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 9, 2, STMT)                                 \
   LAM_CT_CASE(T_, L2N, L2B, THR, 11, 1, STMT)                                \
-  else if (L2N < 0) {                                                        \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 42, 0, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 41, 1, STMT)                                \
+  LAM_CT_CASE(T_, L2N, L2B, THR, 41, 0, STMT)                                \
+  else if (L2N >= 32) {                                                        \
     constexpr int LN = -1, LB = 0;                                           \
     STMT;                                                                    \
   }                                                                          \
@@ -501,10 +514,10 @@ static hipError_t prep(Kern k, size_t lds) {
     STMT;                                                                    \
   }
 
-// length code of a transform of N = 2^l or 3 2^l points (l = its trailing zero bits): l, or -1
+// length code of a transform of N = 2^l or 3 2^l points (l = its trailing zero bits): l, or 32 + l
 static int len_code(int N) {
   const int l = __builtin_ctz((unsigned)N);
-  return N == (1 << l) ? l : -1;
+  return N == (1 << l) ? l : 32 + l;
 }
 
 template <typename Kern, typename... Args>
@@ -533,7 +546,7 @@ hipError_t launch_zfwd(const LaunchCfg& c, const void* u, bool real_in, cpx<T>* 
                                y0, in_zs))
       }
     } else {
-      if (code < 0)
+      if (code >= 32)
         e = real_in ? launch(k_zfwd<T, MH, true, -1>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs)
                     : launch(k_zfwd<T, MH, false, -1>, grid, c.z_threads, c.z_lds, s, u, u1, D, tb, c.z_log2TX, y0, in_zs);
       else
@@ -562,7 +575,7 @@ hipError_t launch_zadj(const LaunchCfg& c, const cpx<T>* u1, void* u, bool real_
                                y0, out_zs))
       }
     } else {
-      if (code < 0)
+      if (code >= 32)
         e = real_out ? launch(k_zadj<T, MH, true, -1>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs)
                      : launch(k_zadj<T, MH, false, -1>, grid, c.z_threads, c.z_lds, s, u1, u, D, tb, c.z_log2TX, y0, out_zs);
       else
