@@ -59,6 +59,34 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out: str | None = None) -> str:
+    """liblam with its host code under AddressSanitizer and UBSan (the device code is built as usual;
+    the sanitizer flags apply to the host pass only), for the CPU checks of the C ABI
+    (tests/test_abi_sanitized.py), which never launch a kernel."""
+    out = out or os.path.join(OBJ, "san", "liblam_san.so")
+    odir = os.path.dirname(out)
+    os.makedirs(odir, exist_ok=True)
+    san = []
+    for f in ("-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"):
+        san += ["-Xarch_host", f]
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g", *san]
+
+    def comp(src: str) -> str:
+        obj = os.path.join(odir, src.replace(".hip", ".o"))
+        r = subprocess.run([HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitized build failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(comp, SOURCES))
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out], capture_output=True,
+                       text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{r.stdout}\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -827,6 +827,11 @@ int lam_init(lam_plan* out, const lam_params* p) {
   if (!out || !p) return fail(LAM_ERR_ARG, "null argument");
   *out = nullptr;
   const char* bad = nullptr;
+  // the caller's dtype field is read as the integer it holds: a C caller may store any int there, and
+  // a C++ load of a value outside the enumeration is undefined
+  static_assert(sizeof(lam_dtype) == sizeof(int), "lam_dtype is an int-sized enumeration");
+  int dtype;
+  std::memcpy(&dtype, &p->dtype, sizeof dtype);
   if (!is_len_in(p->n0, 16, 4096) || !is_len_in(p->n1, 16, 4096) || !is_len_in(p->n2, 16, 4096))
     bad = "n0, n1, n2 must be 2^k or 3 2^k in [16, 4096]";
   else if (!is_len_in(p->h, 16, 4096) || !is_len_in(p->w, 16, 4096))
@@ -835,7 +840,7 @@ int lam_init(lam_plan* out, const lam_params* p) {
   else if (!(p->phi >= 0.0 && p->phi < M_PI / 2)) bad = "phi must be in [0, pi/2)";
   else if (p->oversample != 2) bad = "oversample must be 2";
   else if (p->m < 1 || p->m > 8) bad = "m must be in [1, 8]";
-  else if (p->dtype != LAM_C64 && p->dtype != LAM_C128) bad = "dtype must be LAM_C64 or LAM_C128";
+  else if (dtype != LAM_C64 && dtype != LAM_C128) bad = "dtype must be LAM_C64 or LAM_C128";
   else if (p->slab < 0) bad = "slab must be >= 0";
   if (bad) return fail(LAM_ERR_ARG, bad);
   lam_plan_s* P = new (std::nothrow) lam_plan_s();
