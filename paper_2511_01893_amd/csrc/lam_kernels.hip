@@ -42,10 +42,14 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by) {
 // constants (the hot sizes): LN in 1..31 the length 2^LN, LN >= 32 the length 3 2^(LN - 32).
 template <int LN> constexpr bool p2_len() { return LN >= 0 && LN < 32; }
 template <int LN> constexpr int ct_l() { return LN >= 32 ? LN - 32 : LN; }
-template <int LN> constexpr int ct_n() { return LN >= 32 ? 3 << (LN - 32) : 1 << LN; }
+template <int LN> constexpr int ct_n() {   // 0 for the run-time codes
+  if constexpr (LN >= 32) return 3 << (LN - 32);
+  else if constexpr (LN > 0) return 1 << LN;
+  else return 0;
+}
 template <typename T, int LN, int LB> constexpr int ct_threads() {
-  return LN >= 32 ? fft3_threads<vpt<T>(), LN - 32, LB>()
-                  : (((1 << (LN + LB)) / vpt<T>()) < 64 ? 64 : ((1 << (LN + LB)) / vpt<T>()));
+  if constexpr (LN >= 32) return fft3_threads<vpt<T>(), LN - 32, LB>();
+  else return ((1 << (LN + LB)) / vpt<T>()) < 64 ? 64 : ((1 << (LN + LB)) / vpt<T>());
 }
 template <typename T, int LN, int LB> __device__ __forceinline__ int block_threads() {
   if constexpr (LN > 0) return ct_threads<T, LN, LB>();
