@@ -22,11 +22,14 @@ Prints one JSON line.  Besides the contract fields it reports:
 from __future__ import annotations
 
 import argparse
+import csv
 import json
 import math
 import os
+import re
 import sys
 import time
+from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -347,6 +350,167 @@ def measured_traffic(workload: str, kernel: str, slab: int):
     return t["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
+# ---------------------------------------------------------------- profile summaries (profiles/)
+PROF_SHORT = {"k_zfwd": "zfwd", "k_ycol_fwd": "ycol_fwd", "k_xrow_fwd": "xrow_fwd", "k_gather": "gather",
+         "k_rowfft": "rowfft", "k_colfft": "colfft", "k_scatter_fx": "scatter", "k_scatter": "scatter",
+         "k_xrow_adj": "xrow_adj", "k_ycol_adj": "ycol_adj", "k_zadj": "zadj"}
+PROF_ORDER = ["zfwd", "ycol_fwd", "xrow_fwd", "gather", "rowfft", "colfft", "scatter", "xrow_adj", "ycol_adj", "zadj"]
+PROF_COPY = "__amd_rocclr_copyBuffer"
+
+
+def prof_short(name):
+    m = re.search(r"lam::(k_[a-z_]+)<", name)
+    return PROF_SHORT.get(m.group(1)) if m else None
+
+
+def prof_stats(path):
+    out, total = {}, 0.0
+    for r in csv.DictReader(open(path)):
+        total += float(r["TotalDurationNs"])
+        k = prof_short(r["Name"])
+        if k:
+            c, t = out.get(k, (0, 0.0))
+            out[k] = (c + int(r["Calls"]), t + float(r["TotalDurationNs"]))
+    return out, total
+
+
+def prof_counters(path):
+    per = defaultdict(lambda: defaultdict(list))
+    copies = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        v = float(r["Counter_Value"])
+        if r["Kernel_Name"] == PROF_COPY:
+            copies[(r["Dispatch_Id"], r["Counter_Name"])].append(v)
+            continue
+        k = prof_short(r["Kernel_Name"])
+        if k:
+            per[k][(r["Dispatch_Id"], r["Counter_Name"])].append(v)
+    # a dispatch's counter summed over its instances (XCDs / shader engines), then averaged over dispatches
+    avg = {}
+    for k, d in per.items():
+        by = defaultdict(list)
+        for (disp, c), vals in d.items():
+            by[c].append(sum(vals))
+        avg[k] = {c: sum(v) / len(v) for c, v in by.items()}
+    cp = defaultdict(list)
+    for (disp, c), vals in copies.items():
+        cp[c].append(sum(vals))
+    return avg, cp
+
+
+def prof_bench_json(log):
+    for line in open(log):
+        if line.startswith("{"):
+            return json.loads(line)
+    raise RuntimeError(f"no JSON line in {log}")
+
+
+def summarize_profiles(d):
+    """Writes profiles/kernels_lam512.md, profiles/traffic_lam512.json and profiles/kernels_lam1536.md
+    from the rocprofv3 output under d (kt512/, fetch/, write/, sq1/, sq2/, kt1536/ and the logs of
+    the profiled bench runs, kt512.log and kt1536.log)."""
+    HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+    kt, total = prof_stats(os.path.join(d, "kt512", "kt_kernel_stats.csv"))
+    res = prof_bench_json(os.path.join(d, "kt512.log"))
+    cfg = res["config"]
+    n, nt, h, slab = cfg["n"], cfg["ntheta"], cfg["det"], cfg["slab"]
+
+    class P:
+        n0 = n1 = n2 = n
+        ntheta, w = nt, h
+    P.h = h
+    fetch, fcp = prof_counters(os.path.join(d, "fetch", "fetch_counter_collection.csv"))
+    write, wcp = prof_counters(os.path.join(d, "write", "write_counter_collection.csv"))
+    # calibration: the 1 GiB copy (the largest copy dispatch) moves 1 GiB each way
+    wmax = max(wcp["WRITE_SIZE"])
+    fmax = max(fcp["FETCH_SIZE"])
+    sf, sw = (1 << 20) / fmax, (1 << 20) / wmax
+    sq1, _ = prof_counters(os.path.join(d, "sq1", "sq1_counter_collection.csv"))
+    sq2, _ = prof_counters(os.path.join(d, "sq2", "sq2_counter_collection.csv"))
+    traffic = {"workload": "lam512", "slab": slab, "source_sha256": source_digest(), "scale_fetch": sf,
+               "scale_write": sw,
+               "calibration": f"1 GiB device-to-device copy ({PROF_COPY}): FETCH_SIZE {fmax:.0f} KiB, WRITE_SIZE {wmax:.0f} KiB",
+               "kernels": {}}
+    rows = []
+    for k in PROF_ORDER:
+        calls, tns = kt[k]
+        avg_us = tns / calls / 1e3
+        alg = kernel_units(k, P, 8, 8, slab)
+        fk, wk = fetch[k]["FETCH_SIZE"], write[k]["WRITE_SIZE"]
+        hbm = (fk * sf + wk * sw) * 1024
+        traffic["kernels"][k] = {"fetch_kib_per_launch": fk, "write_kib_per_launch": wk, "hbm_bytes_per_launch": int(hbm)}
+        rows.append((k, calls, avg_us, 100 * tns / total, alg, alg / (avg_us * 1e3), hbm, hbm / (avg_us * 1e3)))
+    json.dump(traffic, open(os.path.join(HERE, "traffic_lam512.json"), "w"), indent=1)
+    dom = res["roofline"]
+    pair_kernel_ms = sum(kern["ms_total_per_step"] for kern in res["kernels"].values())
+    L = []
+    L.append("# Kernel profile: lam512 forward + adjoint pair (complex64)\n")
+    L.append("Workload: 512^3 volume, 512 angles, tilt 30 deg, 512 x 512 detector, R = 2, m = 4, "
+             f"k_v slabs of {slab}.\n")
+    L.append("Commands (from a directory outside the tree, `TMPDIR=/tmp`; `R` = the repository):\n")
+    L.append("```")
+    b5 = "--steps 5 --warmup 2 --no-cpu --no-check --no-fp64 --no-memo --no-offload --calib-copy"
+    b1 = "--steps 1 --warmup 1 --no-cpu --no-check --no-fp64 --no-memo --no-offload --calib-copy"
+    L.append(f"rocprofv3 --kernel-trace --stats --output-format csv -d prof/kt512 -o kt -- python3 $R/bench.py {b5}")
+    L.append(f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d prof/fetch -o fetch -- python3 $R/bench.py {b1}")
+    L.append(f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d prof/write -o write -- python3 $R/bench.py {b1}")
+    L.append("rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+             f"SQ_WAIT_INST_LDS SQ_INSTS_VMEM_RD --output-format csv -d prof/sq1 -o sq1 -- python3 $R/bench.py {b1}")
+    L.append("rocprofv3 --pmc SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VALU "
+             "SQ_INSTS_LDS_ATOMIC SQ_WAIT_ANY SQ_INSTS_SMEM SQ_INSTS_VMEM_WR --output-format csv -d prof/sq2 -o sq2 "
+             f"-- python3 $R/bench.py {b1}")
+    L.append("python3 $R/bench.py --summarize-profiles prof")
+    L.append("```\n")
+    L.append(f"Kernel trace ({kt['zfwd'][0]} pairs: warm-up, timed, and bench's per-kernel event pass; the gather and "
+             "spread also run in the frequency-domain pair):\n")
+    L.append("| kernel | calls | avg us | % of GPU time | algorithmic bytes / launch | algorithmic GB/s | "
+             "HBM bytes / launch (counters) | HBM GB/s |")
+    L.append("|---|---|---|---|---|---|---|---|")
+    for k, calls, avg_us, pct, alg, ag, hbm, hg in rows:
+        L.append(f"| {k} | {calls} | {avg_us:.1f} | {pct:.1f} | {alg / 1e6:.1f} MB | {ag:.0f} | {hbm / 1e6:.1f} MB | {hg:.0f} |")
+    L.append("")
+    L.append(f"The bench line of the traced run: pair {res['ms_per_step']:.3f} ms ({res['value']:.2f} pairs/s); "
+             f"kernel time per pair from its HIP events {pair_kernel_ms:.2f} ms. Dominant kernel "
+             f"`{dom['kernel']}`: {dom['avg_launch_ms'] * 1e3:.1f} us per launch by the bench's HIP events, "
+             f"{dict((r[0], r[2]) for r in rows)[dom['kernel']]:.1f} us by the trace above "
+             "(the trace's average also holds the frequency-domain pair's launches).\n")
+    L.append(f"HBM byte counters are scaled by a plain 1 GiB copy measured in the same runs: FETCH_SIZE reads "
+             f"{fmax:.0f} KiB for the copy's 1048576 KiB (factor {sf:.3f}), WRITE_SIZE {wmax:.0f} KiB (factor {sw:.3f}).\n")
+    L.append("SQ counters, per dispatch (summed over the counter instances, averaged over dispatches):\n")
+    cols = [("WAVES", sq1, "SQ_WAVES"), ("INSTS_VALU", sq1, "SQ_INSTS_VALU"), ("INSTS_SALU", sq1, "SQ_INSTS_SALU"),
+            ("INSTS_LDS", sq1, "SQ_INSTS_LDS"), ("INSTS_LDS_ATOMIC", sq2, "SQ_INSTS_LDS_ATOMIC"),
+            ("ACTIVE_INST_LDS", sq2, "SQ_ACTIVE_INST_LDS"), ("ACTIVE_INST_VALU", sq2, "SQ_ACTIVE_INST_VALU"),
+            ("LDS_BANK_CONFLICT", sq2, "SQ_LDS_BANK_CONFLICT"), ("WAIT_INST_LDS", sq1, "SQ_WAIT_INST_LDS"),
+            ("WAVE_CYCLES", sq1, "SQ_WAVE_CYCLES"), ("WAIT_ANY", sq2, "SQ_WAIT_ANY"), ("BUSY_CYCLES", sq1, "SQ_BUSY_CYCLES")]
+    L.append("| kernel | " + " | ".join(c[0] for c in cols) + " |")
+    L.append("|---|" + "---|" * len(cols))
+    for k in PROF_ORDER:
+        L.append(f"| {k} | " + " | ".join(f"{src[k].get(cn, float('nan')):.3g}" for _, src, cn in cols) + " |")
+    open(os.path.join(HERE, "kernels_lam512.md"), "w").write("\n".join(L) + "\n")
+
+    kt15, total15 = prof_stats(os.path.join(d, "kt1536", "kt_kernel_stats.csv"))
+    r15 = prof_bench_json(os.path.join(d, "kt1536.log"))
+    c15 = r15["config"]
+    M = ["# Kernel profile: lam1536 forward + adjoint pair (complex64)\n",
+         f"Workload: 1536^3 volume, 1536 angles, tilt 20 deg, 1536 x 1536 detector, R = 2, m = 4, k_v slabs of {c15['slab']} "
+         "(transforms of 3072 = 3·2^10 and 1536 = 3·2^9 points).\n",
+         "```",
+         "rocprofv3 --kernel-trace --stats --output-format csv -d prof/kt1536 -o kt -- python3 $R/bench.py --workload lam1536 "
+         "--steps 2 --warmup 1 --no-cpu --no-check --no-fp64 --no-memo --no-offload",
+         "python3 $R/bench.py --summarize-profiles prof",
+         "```\n",
+         "| kernel | calls | avg us | % of GPU time |", "|---|---|---|---|"]
+    for k in PROF_ORDER:
+        calls, tns = kt15[k]
+        M.append(f"| {k} | {calls} | {tns / calls / 1e3:.1f} | {100 * tns / total15:.1f} |")
+    M.append("")
+    M.append(f"The bench line of the traced run: pair {r15['ms_per_step']:.1f} ms ({r15['value']:.3f} pairs/s); dominant "
+             f"kernel `{r15['roofline']['kernel']}` {r15['roofline']['avg_launch_ms'] * 1e3:.1f} us per launch by the "
+             "bench's HIP events.")
+    open(os.path.join(HERE, "kernels_lam1536.md"), "w").write("\n".join(M) + "\n")
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,7 +527,12 @@ def main():
                     help="also time three full FP64 oracle pairs at 256^3 (several minutes of host time)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference kernel for HBM byte counters)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write the summaries in profiles/ from the rocprofv3 output under DIR, then exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the operator runs on one GPU: --gpus must be 1 (the sharded design is described, not built)", "n_gpus": args.gpus}))
         sys.exit(2)
