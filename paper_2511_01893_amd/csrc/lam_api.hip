@@ -116,9 +116,9 @@ int fft_threads(long N, long B, size_t csize) {
   return (int)std::max<long>(64, (N * B + vp * 64 - 1) / (vp * 64) * 64);
 }
 
-// column blocks of TX transforms of length N (TX a power of two dividing ncols)
-void col_cfg(long N, int ncols, size_t csize, int& log2TX, int& threads, size_t& lds) {
-  int TX = 16;
+// column blocks of TX <= txmax transforms of length N (TX a power of two dividing ncols)
+void col_cfg(long N, int ncols, size_t csize, int& log2TX, int& threads, size_t& lds, int txmax = 16) {
+  int TX = txmax;
   const int vp = vpt_of(csize);
   while (TX > 1 && (TX > ncols || ncols % TX || N * TX * (long)csize > 131072 || N * TX / vp > 1024)) TX >>= 1;
   log2TX = ilog2(TX);
@@ -324,7 +324,10 @@ int build(lam_plan_s* P) {
   D.xy.h = p.h;
   // launch shapes
   LaunchCfg& c = P->cfg;
-  col_cfg(P->M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds);
+  // z and y steps: at most 8 columns per block, so that two blocks share a CU (one loads while the
+  // other runs its FFT); with the XCD-aware block order the 64-byte row pieces of neighbouring blocks
+  // meet in one L2 (measured at 512^3: z steps 2.64 -> 2.38 ms, y steps 2.05 -> 1.93 ms per pair)
+  col_cfg(P->M0, p.n2, P->csize, c.z_log2TX, c.z_threads, c.z_lds, 8);
   // the z adjoint stages h samples per column in the same LDS, and both z kernels stage the per-row
   // bases and offsets and the inverse runs after it: shrink the tile until everything fits
   const size_t z_tables = (size_t)p.h * (sizeof(int) + P->rsize) + 2 * (size_t)P->M0 * sizeof(unsigned);
@@ -335,7 +338,7 @@ int build(lam_plan_s* P) {
   }
   c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize + z_tables;
   if (c.z_lds > kLdsMax) return fail(LAM_ERR_ARG, "z kernels do not fit the LDS");
-  col_cfg(P->M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds);
+  col_cfg(P->M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds, 8);
   row_cfg(P->M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
   row_cfg(p.w, p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
   col_cfg(p.h, p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
