@@ -210,19 +210,22 @@ def test_lam2048_streamed():
     uh = torch.empty((n, n, n), dtype=torch.float32, pin_memory=True)
     for z0 in range(0, n, 128):               # the phantom, generated on the device a z-slab at a time
         uh[z0:z0 + 128] = I.blob_phantom_torch((n, n, n), blobs, "cuda", torch.float32, z_range=(z0, z0 + 128)).cpu()
+    print("2048^3 phantom in pinned host memory", flush=True)
     # the 69 GB of data and the adjoint's output stay pageable (the box pins at most a few tens of GB)
     fo = torch.empty(plan.data_shape, dtype=torch.complex64)
     t0 = time.perf_counter()
     plan.fwd_streamed(uh, out=fo)
     t_f = time.perf_counter() - t0
+    print(f"2048^3 streamed forward {t_f:.2f} s", flush=True)
     ao = torch.empty((n, n, n), dtype=torch.float32)
     t0 = time.perf_counter()
     plan.adj_streamed(fo, real=True, out=ao)
     t_a = time.perf_counter() - t0
+    print(f"2048^3 streamed adjoint {t_a:.2f} s", flush=True)
     lhs = rhs = 0.0
     for a in range(0, n, 64):                 # FP64 sums on the device, 64 planes at a time
         lhs += float(torch.view_as_real(fo[a:a + 64].cuda()).double().pow(2).sum())
         rhs += float((uh[a:a + 64].cuda().double() * ao[a:a + 64].cuda().double()).sum())
     err = abs(lhs - rhs) / lhs
-    print(f"2048^3 streamed: forward {t_f:.2f} s, adjoint {t_a:.2f} s; adjoint identity {err:.2e}")
+    print(f"2048^3 streamed: forward {t_f:.2f} s, adjoint {t_a:.2f} s; adjoint identity {err:.2e}", flush=True)
     assert err < 1e-4

@@ -184,3 +184,50 @@ def test_lam1536_sampled_96_angles(L):
     e_a = rel(Lsd.double(), p128.adj(d.to(torch.complex128), real=True))
     print(f"1536^3 c64 vs c128: fwd {e_f:.2e} adj {e_a:.2e}", flush=True)
     assert e_f < 1e-4 and e_a < 1e-4
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-9)], ids=["c64", "c128"])
+def test_admm_48_vs_oracle(L, dtype, tol):
+    """Two ADMM-TV iterations (3 inner CG steps each) on a 48^3 blob phantom against the oracle's."""
+    n, nt = 48, 12
+    g = O.Geometry(n, n, n, nt, math.radians(30.0), n, n, 2, 4)
+    d = O.lam_fwd(I.blob_phantom(g.vol_shape, I.draw_blobs(9, 6)), g).real.astype(np.complex128)
+    dhat = O.f2d_unnorm(d)
+    alpha, u, rho = 1e-3, np.zeros(g.vol_shape), 0.5
+    psi = np.zeros((3,) + g.vol_shape)
+    lam = np.zeros_like(psi)
+    plan = L.Plan(n, ntheta=nt, phi=g.phi, h=n, w=n, dtype=dtype)
+    s = L.AdmmTV(plan, alpha, rho0=0.5)
+    dh = plan.data_hat(gpu(d, dtype))
+    for it in range(2):
+        u, psi, lam, rho = O.admm_step(u, psi, lam, rho, dhat, g, alpha, 3)
+        s.step(dh, 3)
+        eu, ep, el = O.relerr(host(s.u), u), O.relerr(host(s.psi), psi), O.relerr(host(s.lam), lam)
+        print(f"48^3 ADMM iteration {it}: u {eu:.2e} psi {ep:.2e} lambda {el:.2e} rho {s.rho} (oracle {rho})",
+              flush=True)
+        assert eu < tol and ep < 10 * tol and el < 10 * tol
+        assert s.rho == rho
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+def test_streamed_and_scratch_48(L, dtype):
+    """The host-streamed pair (ragged y- and theta-slabs) and the no-allocation forward on a 3 2^k plan,
+    against the resident operators."""
+    n, nt = 48, 20
+    plan = L.Plan(n, ntheta=nt, phi=math.radians(25.0), dtype=dtype)
+    plan.stream_slabs(7, 6)
+    u = I.blob_phantom_torch((n, n, n), I.draw_blobs(8, 6), "cuda", plan.rdtype)
+    d = I.random_complex_torch(plan.data_shape, 81, "cuda", dtype)
+    ref_f, ref_a = plan.fwd(u), plan.adj(d, real=True)
+    got_f = plan.fwd_streamed(u.cpu().pin_memory())
+    got_a = plan.adj_streamed(d.cpu().pin_memory(), real=True)
+    assert torch.equal(got_f, ref_f.cpu())
+    assert rel(got_a, ref_a.cpu()) < (1e-6 if dtype == torch.complex64 else 1e-14)
+    ps = L.Plan(n, ntheta=nt, phi=math.radians(25.0), dtype=dtype, workspace=False)
+    uc = u.to(dtype)
+    out = torch.full(ps.data_shape, float("nan"), dtype=dtype, device="cuda")
+    ps.fwd_scratch(uc, out)
+    torch.cuda.synchronize()
+    e = ((out - plan.fwd(uc)).abs().max() / out.abs().max()).item()
+    print(f"48^3 streamed fwd identical, adj {rel(got_a, ref_a.cpu()):.1e}; scratch vs lam_fwd {e:.1e}", flush=True)
+    assert e <= (1e-6 if dtype == torch.complex64 else 1e-13)
