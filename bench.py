@@ -523,6 +523,8 @@ def main():
     ap.add_argument("--slab", type=int, default=0, help="k_v slices per 2D-step slab (0: automatic)")
     ap.add_argument("--no-memo", action="store_true", help="skip the memoized ADMM-TV study")
     ap.add_argument("--no-offload", action="store_true", help="skip the ADMM-Offload planning study")
+    ap.add_argument("--no-1536", action="store_true",
+                    help="skip the pair at the 1.5K^3 shape (1536^3, 1536 angles, 1536^2 detector)")
     ap.add_argument("--oracle-c2", action="store_true",
                     help="also time three full FP64 oracle pairs at 256^3 (several minutes of host time)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -674,6 +676,28 @@ def main():
         t = time.perf_counter()
         result["offload"] = offload_study(lam, I, dev, args.workload)
         log(f"[bench] offload study in {time.perf_counter() - t:.1f} s")
+        torch.cuda.empty_cache()
+
+    if not args.no_1536 and args.workload == "lam512":
+        # the paper's second default dataset shape: transforms of 3 2^k points; measured after the
+        # 512^3 objects are freed (its plan, volume and data take ~130 GB)
+        t = time.perf_counter()
+        del plan, u, d, d64, u64
+        torch.cuda.empty_cache()
+        w15 = I.WORKLOADS["lam1536"]
+        n15 = w15["n"]
+        p15 = lam.Plan(n15, ntheta=w15["ntheta"], phi=math.radians(w15["phi_deg"]), h=w15["det"], w=w15["det"],
+                       dtype=torch.complex64, device=dev)
+        u15 = I.blob_phantom_torch((n15, n15, n15), I.draw_blobs(w15["seed"], 64), dev, torch.float32)
+        d15 = I.random_complex_torch(p15.data_shape, w15["seed"] + 200, dev, torch.complex64)
+        ms15, _, _, _ = time_pairs(p15, u15.to(torch.complex64), d15, 3, 1)
+        result["lam1536"] = {"workload": "1536^3 volume, 1536 angles, tilt 20 deg, 1536x1536 detector, R=2, m=4, "
+                                         "c64 (transforms of 3072 = 3 2^10 and 1536 = 3 2^9 points)",
+                             "ms_per_pair": ms15, "pairs_per_s": 1000.0 / ms15, "steps": 3,
+                             "pair_hbm_frac": 2 * algorithmic_bytes(n15, n15, n15, w15["ntheta"], n15, n15, 8, 8)
+                             / (ms15 * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+        log(f"[bench] 1536^3 pair {ms15:.1f} ms in {time.perf_counter() - t:.1f} s")
+        del p15, u15, d15
         torch.cuda.empty_cache()
 
     if not args.no_cpu:
