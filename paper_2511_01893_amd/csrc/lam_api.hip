@@ -339,9 +339,13 @@ int build(lam_plan_s* P) {
   c.z_lds = (size_t)std::max(P->M0, p.h) * ((size_t)1 << c.z_log2TX) * P->csize + z_tables;
   if (c.z_lds > kLdsMax) return fail(LAM_ERR_ARG, "z kernels do not fit the LDS");
   col_cfg(P->M1, p.n2, P->csize, c.y_log2TX, c.y_threads, c.y_lds, 8);
+  // y kernels whose columns each fit one wave hold them column-major with a skewed pitch of
+  // N + N/8 + 1 elements (one pad slot per 8, plus one)
+  c.y_lds = std::max(c.y_lds, ((size_t)1 << c.y_log2TX) * ((size_t)P->M1 + P->M1 / 8 + 1) * P->csize);
   row_cfg(P->M2, (long)S * P->M1, P->csize, c.x_log2RB, c.x_threads, c.x_lds);
   row_cfg(p.w, p.h, P->csize, c.r_log2RB, c.r_threads, c.r_lds);
   col_cfg(p.h, p.w, P->csize, c.c_log2TX, c.c_threads, c.c_lds);
+  c.c_lds = std::max(c.c_lds, ((size_t)1 << c.c_log2TX) * ((size_t)p.h + p.h / 8 + 1) * P->csize);
   c.g_log2TS = ilog2(TS);
   // gather: the tile plus its (2m-1) halo; scatter: two FP64 planes of the tile (pitch TS + 8)
   const size_t Pt = TS + 2 * m - 1;

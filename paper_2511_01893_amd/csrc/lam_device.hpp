@@ -262,6 +262,63 @@ __device__ __forceinline__ void lds_fft3(cpx<T>* buf, int a, int log2nb, int sp,
   }
 }
 
+// Row FFTs with one wave per row (or per few rows): when a wave's 64 lanes hold whole rows
+// (RPW = 64 VPT / N rows of N = 2^LOG2N points, row-major with one pad slot per 8 elements), each
+// wave runs every stage on its own rows, and the stages are ordered by wave-level fences instead of
+// work-group barriers: the LDS operations of one wave complete in order, so its reads after a fence
+// see its writes before it, and no wave waits for another.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// PITCH: elements from one row to the next (lpad(N) for row-major buffers; column kernels hold each
+// column as a row of a column-major buffer and skew the pitch by one slot, lpad(N) + 1, so that the
+// staging writes of neighbouring columns fall in different banks).
+template <int LOG2N> constexpr int wave_pitch(bool skew) { return (1 << LOG2N) + ((1 << LOG2N) >> 3) + (skew ? 1 : 0); }
+
+template <typename T, int R, int VPT, int LOG2N, int LOG2NS, int PITCH>
+__device__ __forceinline__ void fft_stage_wave(cpx<T>* buf, const cpx<T>* __restrict__ tw, int log2tw) {
+  constexpr int LR = (R == 8) ? 3 : (R == 4 ? 2 : 1);
+  constexpr int LOG2NBF = LOG2N - LR, NBF = 1 << LOG2NBF, NS = 1 << LOG2NS;
+  constexpr int RPW = (64 * VPT) >> LOG2N;         // rows per wave
+  constexpr int IT = VPT / R;                      // butterflies per lane: RPW NBF / 64
+  static_assert(RPW >= 1 && (RPW << LOG2NBF) == 64 * IT, "a wave holds whole rows");
+  const int lane = threadIdx.x & 63, row0 = (threadIdx.x >> 6) * RPW;
+  cpx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int q = lane + 64 * it, b = row0 + (q >> LOG2NBF), j = q & (NBF - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[it][r] = buf[b * PITCH + lpad<true>(j + r * NBF)];
+  }
+  wave_lds_sync();
+  const int twsh = log2tw - (LOG2NS + LR);
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int q = lane + 64 * it, b = row0 + (q >> LOG2NBF), j = q & (NBF - 1);
+    const int k = j & (NS - 1);
+    twiddle_dft<T, R>(v[it], tw, k, twsh);
+    const int idxD = ((j >> LOG2NS) << (LOG2NS + LR)) + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[b * PITCH + lpad<true>(idxD + r * NS)] = v[it][r];
+  }
+  wave_lds_sync();
+}
+
+template <typename T, int VPT, int LOG2N, int PITCH = wave_pitch<LOG2N>(false), int REM = LOG2N, int LOG2NS = 0>
+__device__ __forceinline__ void lds_fft_wave(cpx<T>* buf, const cpx<T>* __restrict__ tw, int log2tw) {
+  if constexpr (REM >= 3) {
+    fft_stage_wave<T, 8, VPT, LOG2N, LOG2NS, PITCH>(buf, tw, log2tw);
+    lds_fft_wave<T, VPT, LOG2N, PITCH, REM - 3, LOG2NS + 3>(buf, tw, log2tw);
+  } else if constexpr (REM == 2) {
+    fft_stage_wave<T, 4, VPT, LOG2N, LOG2NS, PITCH>(buf, tw, log2tw);
+  } else if constexpr (REM == 1) {
+    fft_stage_wave<T, 2, VPT, LOG2N, LOG2NS, PITCH>(buf, tw, log2tw);
+  }
+}
+
 // The 3 2^A-point FFT with A, the batch NB = 2^LOG2NB and the layout fixed at compile time (the
 // hot sizes of the 3 2^k grids): every division by 3 2^s is by a constant, the stages unroll, and
 // the work-group size is the launch's, max(64, N NB / VPT rounded up to whole waves).  COLS as for

@@ -63,6 +63,19 @@ __device__ __forceinline__ void fft_cols(cpx<T>* buf, int lN, int log2TX, const 
   else if constexpr (LN < 0) lds_fft3<T, vpt<T>()>(buf, lN, log2TX, 1 << log2TX, 1, true, tb.tw3, tb.log2tw3, nth);
   else lds_fft<T, vpt<T>()>(buf, lN, log2TX, 1 << log2TX, 1, true, tb.tw, tb.log2tw, nth);
 }
+// Row kernels with one wave per row (or per few rows): compile-time power-of-two lengths whose rows
+// fit a wave (N <= 64 VPT) and blocks of whole waves' rows.  The staging, the FFT stages and the store
+// then touch only the wave's own rows, ordered by wave-level fences (no work-group barrier).
+template <typename T, int LN, int LB> constexpr bool wave_rows() {
+  if constexpr (LN > 0 && LN < 32) return (64 * vpt<T>() >= (1 << LN)) && ((1 << LB) * (1 << LN) >= 64 * vpt<T>());
+  else return false;
+}
+
+// Column kernels with one wave per column (or per few columns): the same condition on the column
+// length; the block's coalesced loads stage the columns into a column-major buffer (pitch
+// wave_pitch<LN>(true)), one work-group barrier, the wave-ordered stages, one barrier, the stores.
+template <typename T, int LN, int LB> constexpr bool wave_cols() { return wave_rows<T, LN, LB>(); }
+
 // row blocks: element (p, b) at b N + p, one pad slot per 8 elements; N = 2^lN, or 3 2^lN for LN = -1
 template <typename T, int LN, int LB>
 __device__ __forceinline__ void fft_rows(cpx<T>* buf, int lN, int N, int log2RB, const Tables<T>& tb, int nth) {
@@ -245,6 +258,28 @@ __global__ __launch_bounds__(1024) void k_ycol_fwd(const cpx<T>* __restrict__ u1
   if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
+  if constexpr (wave_cols<T, LN, LB>()) {
+    constexpr int PC = wave_pitch<LN>(true);
+    cpx<T> v[vpt<T>()];
+#pragma unroll
+    for (int it = 0; it < vpt<T>() / 2; ++it)   // the input fills n1 = M1 / 2 rows
+      v[it] = u1[((size_t)k * n1 + ((tid + it * nth) >> LB)) * n2 + x0 + ((tid + it * nth) & (TX - 1))];
+#pragma unroll
+    for (int it = 0; it < vpt<T>() / 2; ++it) {
+      const int e = tid + it * nth, a = e >> LB, b = e & (TX - 1);
+      buf[b * PC + lpad<true>(n1 / 2 + a)] = zero;
+      buf[b * PC + lpad<true>((a - n1 / 2) & (M1 - 1))] = v[it] * (tb.cy[a] * tb.cx[x0 + b]);
+    }
+    __syncthreads();
+    lds_fft_wave<T, vpt<T>(), LN, PC>(buf, tb.tw, tb.log2tw);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = tid + it * nth, q = e >> LB, b = e & (TX - 1);
+      Tb[((size_t)kk * M1 + q) * n2 + x0 + b] = buf[b * PC + lpad<true>(q)];
+    }
+    return;
+  }
   for (int e = tid; e < (M1 - n1) * TX; e += nth) buf[(n1 / 2) * TX + e] = zero;
   {
     cpx<T> v[vpt<T>()];
@@ -284,6 +319,29 @@ __global__ __launch_bounds__(1024) void k_ycol_adj(const cpx<T>* __restrict__ Tb
   const int x0 = bx * TX, k = k0 + kk;
   if (D.skip.skip(kk)) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
+  if constexpr (wave_cols<T, LN, LB>()) {
+    constexpr int PC = wave_pitch<LN>(true);
+    cpx<T> v[vpt<T>()];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it)
+      v[it] = Tb[((size_t)kk * M1 + ((tid + it * nth) >> LB)) * n2 + x0 + ((tid + it * nth) & (TX - 1))];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = tid + it * nth;
+      buf[(e & (TX - 1)) * PC + lpad<true>(e >> LB)] = conj(v[it]);
+    }
+    __syncthreads();
+    lds_fft_wave<T, vpt<T>(), LN, PC>(buf, tb.tw, tb.log2tw);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < vpt<T>() / 2; ++it) {
+      const int e = tid + it * nth, a = e >> LB, b = e & (TX - 1);
+      const cpx<T> w = buf[b * PC + lpad<true>((a - n1 / 2) & (M1 - 1))];
+      const T c = tb.cy[a] * tb.cx[x0 + b];
+      u1[((size_t)k * n1 + a) * n2 + x0 + b] = mk(w.x * c, -w.y * c);
+    }
+    return;
+  }
   {
     cpx<T> v[vpt<T>()];
 #pragma unroll
@@ -318,6 +376,28 @@ __global__ __launch_bounds__(1024) void k_xrow_fwd(const cpx<T>* __restrict__ Tb
   if (D.skip.hit && D.skip.skip(D.slice_of(r0))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
   const cpx<T> zero = mk((T)0, (T)0);
+  if constexpr (wave_rows<T, LN, LB>()) {
+    // the wave's rows: RPW rows of M2 points from RPW rows of n2 inputs, contiguous in memory
+    constexpr int RPW = (64 * vpt<T>()) >> LN, NI = RPW * (M2 / 2) / 64;
+    const int lane = tid & 63, row0 = (tid >> 6) * RPW;
+    cpx<T> v[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) v[it] = Tb[((size_t)r0 + row0) * n2 + lane + 64 * it];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int e = lane + 64 * it, b = row0 + e / n2, a = e % n2;
+      buf[lpad<true>(b * M2 + n2 / 2 + a)] = zero;
+      buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))] = v[it];
+    }
+    wave_lds_sync();
+    lds_fft_wave<T, vpt<T>(), LN>(buf, tb.tw, tb.log2tw);
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = row0 * M2 + lane + 64 * it;
+      Gb[(size_t)r0 * M2 + e] = buf[lpad<true>(e)];
+    }
+    return;
+  }
   // R = 2: the padded positions of each row are [n2/2, M2 - n2/2), n2 of them
   {
     cpx<T> v[vpt<T>()];
@@ -353,6 +433,23 @@ __global__ __launch_bounds__(1024) void k_xrow_adj(const cpx<T>* __restrict__ Gb
   const int r0 = blockIdx.x * RB;   // slab rows: at most h M1 < 2^31
   if (D.skip.hit && D.skip.skip(D.slice_of(r0))) return;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
+  if constexpr (wave_rows<T, LN, LB>()) {
+    constexpr int RPW = (64 * vpt<T>()) >> LN, NO = RPW * (M2 / 2) / 64;
+    const int lane = tid & 63, row0 = (tid >> 6) * RPW;
+    cpx<T> v[vpt<T>()];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) v[it] = Gb[((size_t)r0 + row0) * M2 + lane + 64 * it];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) buf[lpad<true>(row0 * M2 + lane + 64 * it)] = conj(v[it]);
+    wave_lds_sync();
+    lds_fft_wave<T, vpt<T>(), LN>(buf, tb.tw, tb.log2tw);
+#pragma unroll
+    for (int it = 0; it < NO; ++it) {
+      const int e = lane + 64 * it, b = row0 + e / n2, a = e % n2;
+      Tb[((size_t)r0 + b) * n2 + a] = conj(buf[lpad<true>(b * M2 + ((a - n2 / 2) & (M2 - 1)))]);
+    }
+    return;
+  }
   {
     cpx<T> v[vpt<T>()];
 #pragma unroll
@@ -390,6 +487,28 @@ __global__ __launch_bounds__(1024) void k_rowfft(const cpx<T>* in, cpx<T>* out, 
   const int RB = 1 << log2RB, L = LN > 0 ? ct_n<LN>() : L_;
   const size_t r0 = (size_t)blockIdx.x * RB;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
+  if constexpr (wave_rows<T, LN, LB>()) {
+    constexpr int RPW = (64 * vpt<T>()) >> LN;
+    const int lane = tid & 63, row0 = (tid >> 6) * RPW;
+    const size_t base = (r0 + row0) * L;
+    cpx<T> w[vpt<T>()];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) w[it] = in[base + lane + 64 * it];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = lane + 64 * it, b = row0 + (e >> LN), p = e & (L - 1);
+      const cpx<T> v = inverse ? conj(w[it]) : w[it];
+      buf[lpad<true>(row0 * L + e)] = sgn_parity((int)(r0 & 1) + b + p) > 0 ? v : mk(-v.x, -v.y);
+    }
+    wave_lds_sync();
+    lds_fft_wave<T, vpt<T>(), LN>(buf, tb.tw, tb.log2tw);
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const cpx<T> v = buf[lpad<true>(row0 * L + lane + 64 * it)];
+      out[base + lane + 64 * it] = inverse ? conj(v) : v;
+    }
+    return;
+  }
   {
     cpx<T> w[vpt<T>()];
 #pragma unroll
@@ -426,6 +545,30 @@ __global__ __launch_bounds__(1024) void k_colfft(const cpx<T>* in, cpx<T>* out, 
   const int p0 = bx * TX;
   const size_t base = (size_t)by * H * W;
   const int tid = threadIdx.x, nth = block_threads<T, LN, LB>();
+  if constexpr (wave_cols<T, LN, LB>()) {
+    constexpr int PC = wave_pitch<LN>(true);
+    cpx<T> w[vpt<T>()];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it)
+      w[it] = in[base + (size_t)((tid + it * nth) >> LB) * W + p0 + ((tid + it * nth) & (TX - 1))];
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = tid + it * nth;
+      buf[(e & (TX - 1)) * PC + lpad<true>(e >> LB)] = inverse ? conj(w[it]) : w[it];
+    }
+    __syncthreads();
+    lds_fft_wave<T, vpt<T>(), LN, PC>(buf, tb.tw, tb.log2tw);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = tid + it * nth, a = e >> LB, b = e & (TX - 1);
+      cpx<T> v = buf[b * PC + lpad<true>(a)];
+      if (inverse) v = conj(v);
+      const T sg = sgn_parity(a + p0 + b) > 0 ? scale : -scale;
+      out[base + (size_t)a * W + p0 + b] = v * sg;
+    }
+    return;
+  }
   {
     cpx<T> w[vpt<T>()];
 #pragma unroll
