@@ -449,8 +449,8 @@ def summarize_profiles(d):
              f"k_v slabs of {slab}.\n")
     L.append("Commands (from a directory outside the tree, `TMPDIR=/tmp`; `R` = the repository):\n")
     L.append("```")
-    b5 = "--steps 5 --warmup 2 --no-cpu --no-check --no-fp64 --no-memo --no-offload --calib-copy"
-    b1 = "--steps 1 --warmup 1 --no-cpu --no-check --no-fp64 --no-memo --no-offload --calib-copy"
+    b5 = "--steps 5 --warmup 2 --no-cpu --no-check --no-fp64 --no-memo --no-offload --no-1536 --calib-copy"
+    b1 = "--steps 1 --warmup 1 --no-cpu --no-check --no-fp64 --no-memo --no-offload --no-1536 --calib-copy"
     L.append(f"rocprofv3 --kernel-trace --stats --output-format csv -d prof/kt512 -o kt -- python3 $R/bench.py {b5}")
     L.append(f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d prof/fetch -o fetch -- python3 $R/bench.py {b1}")
     L.append(f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d prof/write -o write -- python3 $R/bench.py {b1}")
