@@ -7,8 +7,9 @@
 // the M1 x M2 grid gets the list of targets whose stencil base floor(s)
 // lies in the tile, sub-sorted into 3 x 3 classes by whether the stencil
 // reaches across the tile's low / high border in x and y.  Each target is
-// listed exactly once (checked on the host: every slice holds n_theta w
-// entries).
+// listed exactly once (checked when the lists are built: every slice holds
+// n_theta w entries, and k_list_check re-classifies every entry and marks it
+// in a per-target bitmap, so a duplicate or a misplaced entry is an error).
 //   k_gather   stages a tile plus its (2m-1) halo in LDS and walks the tile's
 //              list, one lane per target: FP64 coordinates, weights, 2m x 2m
 //              FMA gather, optional fused "- d^" (Algorithm 2).

@@ -36,6 +36,30 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by) {
   bx = l - by * gx;
 }
 
+// 16 bytes of a z block's row of TX columns (two complex64 or one complex128 values): the z
+// stencil kernels move a row as NCH = TX / CW such chunks (ds_read_b128 / global 16-byte stores).
+template <typename T>
+struct alignas(16) Chunk16 {
+  static constexpr int CW = 16 / (int)sizeof(cpx<T>);
+  cpx<T> c[CW];
+};
+template <typename T>
+__device__ __forceinline__ void fma_chunk(Chunk16<T>& a, T w, const Chunk16<T>& g) {
+#pragma unroll
+  for (int e = 0; e < Chunk16<T>::CW; ++e) {
+    a.c[e].x += w * g.c[e].x;
+    a.c[e].y += w * g.c[e].y;
+  }
+}
+// Chunk order of this lane: a thread handles whole rows (64 bytes for eight complex64 columns), so
+// lanes reading chunk c of different rows at once would meet on the banks of that chunk's
+// position; instead lane l starts at chunk s(l), with s sweeping 0 .. NCH - 1 over every 16 lanes,
+// and lane l's c-th access is chunk (c + s(l)) mod NCH.
+template <int NCH>
+__device__ __forceinline__ int chunk_skew() {
+  return (((int)(threadIdx.x & 15) * NCH) >> 4) & (NCH - 1);
+}
+
 // The FFT kernels take a template length code LN and LB (log2 of the transforms per block):
 // LN = 0 selects the general kernel for power-of-two lengths (sizes from the arguments), LN = -1 the
 // general kernel for lengths 3 2^l (the mixed-radix LDS FFT); otherwise the sizes are compile-time
@@ -136,19 +160,66 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   __syncthreads();
   fft_cols<T, LN, LB>(buf, lM0, log2TX, tb, nth);
   const GaussW gw{D.beta};
-  for (int e = tid; e < D.h * TX; e += nth) {
-    const int av = e >> log2TX, b = e & (TX - 1);
-    const int base = zb[av] - MH + 1;
-    const T dl = zd[av];
-    T ax = 0, ay = 0;
+  if constexpr (LN > 0) {
+    // one thread per detector row: its 2m weights once, then the TX columns of each stencil row as
+    // 16-byte chunks.  With at most one row per thread the rows go back through LDS (over the grid,
+    // after a barrier) so that the stores below are coalesced; otherwise straight from registers.
+    using C = Chunk16<T>;
+    constexpr int NCH = (1 << LB) / C::CW, NTH = ct_threads<T, LN, LB>();
+    static_assert(NCH >= 1 && ((1 << LB) % C::CW) == 0, "whole chunks per block row");
+    const int s = chunk_skew<NCH>();
+    const bool staged = D.h <= NTH;
+    for (int av0 = 0; av0 < D.h; av0 += NTH) {
+      const int av = av0 + tid;
+      C acc[NCH];
 #pragma unroll
-    for (int i = 0; i < 2 * MH; ++i) {
-      const T w = gw(dl - (T)(i + 1 - MH), T());
-      const cpx<T> g = buf[wrap1<P2>(base + i, M0) * TX + b];
-      ax += w * g.x;
-      ay += w * g.y;
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int e = 0; e < C::CW; ++e) acc[c].c[e] = mk((T)0, (T)0);
+      if (av < D.h) {
+        const int base = zb[av] - MH + 1;
+        const T dl = zd[av];
+#pragma unroll
+        for (int i = 0; i < 2 * MH; ++i) {
+          const T w = gw(dl - (T)(i + 1 - MH), T());
+          const C* row = reinterpret_cast<const C*>(buf + wrap1<P2>(base + i, M0) * (1 << LB));
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) fma_chunk(acc[c], w, row[(c + s) & (NCH - 1)]);
+        }
+      }
+      if (staged) {
+        __syncthreads();
+        if (av < D.h) {
+          C* dst = reinterpret_cast<C*>(buf + av * (1 << LB));
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) dst[(c + s) & (NCH - 1)] = acc[c];
+        }
+        __syncthreads();
+        for (int e = tid; e < D.h * TX; e += nth) {
+          const int a = e >> LB, b = e & (TX - 1);
+          u1[(size_t)a * plane + (size_t)y * D.n2 + x0 + b] = buf[e];
+        }
+      } else if (av < D.h) {
+        C* dst = reinterpret_cast<C*>(u1 + (size_t)av * plane + (size_t)y * D.n2 + x0);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) dst[(c + s) & (NCH - 1)] = acc[c];
+      }
     }
-    u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b] = mk(ax, ay);
+  } else {
+    for (int e = tid; e < D.h * TX; e += nth) {
+      const int av = e >> log2TX, b = e & (TX - 1);
+      const int base = zb[av] - MH + 1;
+      const T dl = zd[av];
+      T ax = 0, ay = 0;
+#pragma unroll
+      for (int i = 0; i < 2 * MH; ++i) {
+        const T w = gw(dl - (T)(i + 1 - MH), T());
+        const cpx<T> g = buf[wrap1<P2>(base + i, M0) * TX + b];
+        ax += w * g.x;
+        ay += w * g.y;
+      }
+      u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b] = mk(ax, ay);
+    }
   }
 }
 
@@ -200,14 +271,22 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
   }
   __syncthreads();
   const GaussW gw{D.beta};
-  cpx<T> v[vpt<T>()];
-  const int total = M0 * TX;
+  if constexpr (LN > 0) {
+    // one thread per grid point q (QPT of them): each covering row's weight once, then its TX
+    // columns as 16-byte chunks; the grid replaces the staging area after a barrier
+    using C = Chunk16<T>;
+    constexpr int NCH = (1 << LB) / C::CW, NTH = ct_threads<T, LN, LB>(), QPT = (ct_n<LN>() + NTH - 1) / NTH;
+    static_assert(NCH >= 1 && ((1 << LB) % C::CW) == 0, "whole chunks per block row");
+    const int s = chunk_skew<NCH>();
+    C acc[QPT][NCH];
 #pragma unroll
-  for (int it = 0; it < vpt<T>(); ++it) {
-    const int e = tid + it * nth;
-    T ax = 0, ay = 0;
-    if (e < total) {
-      const int q = e >> log2TX, b = e & (TX - 1);
+    for (int j = 0; j < QPT; ++j) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int e = 0; e < C::CW; ++e) acc[j][c].c[e] = mk((T)0, (T)0);
+      const int q = tid + j * NTH;
+      if (q >= M0) continue;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const unsigned run = zr[2 * q + r];
@@ -216,19 +295,52 @@ __global__ __launch_bounds__(1024) void k_zadj(const cpx<T>* __restrict__ u1, vo
           // the stencil tap of row av that lands on q
           const int i = wrap1<P2>(q - zb[av] + MH - 1, M0);
           const T w = gw(zd[av] - (T)(i + 1 - MH), T());
-          const cpx<T> g = buf[av * TX + b];
-          ax += w * g.x;
-          ay += w * g.y;
+          const C* row = reinterpret_cast<const C*>(buf + av * (1 << LB));
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) fma_chunk(acc[j][c], w, row[(c + s) & (NCH - 1)]);
         }
       }
     }
-    v[it] = mk(ax, ay);
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int it = 0; it < vpt<T>(); ++it) {
-    const int e = tid + it * nth;
-    if (e < total) buf[e] = v[it];
+    for (int j = 0; j < QPT; ++j) {
+      const int q = tid + j * NTH;
+      if (q >= M0) continue;
+      C* dst = reinterpret_cast<C*>(buf + q * (1 << LB));
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) dst[(c + s) & (NCH - 1)] = acc[j][c];
+    }
+  } else {
+    cpx<T> v[vpt<T>()];
+    const int total = M0 * TX;
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = tid + it * nth;
+      T ax = 0, ay = 0;
+      if (e < total) {
+        const int q = e >> log2TX, b = e & (TX - 1);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const unsigned run = zr[2 * q + r];
+          const int a0 = (int)(run & 0xffffu), a1 = a0 + (int)(run >> 16);
+          for (int av = a0; av < a1; ++av) {
+            // the stencil tap of row av that lands on q
+            const int i = wrap1<P2>(q - zb[av] + MH - 1, M0);
+            const T w = gw(zd[av] - (T)(i + 1 - MH), T());
+            const cpx<T> g = buf[av * TX + b];
+            ax += w * g.x;
+            ay += w * g.y;
+          }
+        }
+      }
+      v[it] = mk(ax, ay);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < vpt<T>(); ++it) {
+      const int e = tid + it * nth;
+      if (e < total) buf[e] = v[it];
+    }
   }
   __syncthreads();
   fft_cols<T, LN, LB>(buf, lM0, log2TX, tb, nth);

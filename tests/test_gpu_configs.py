@@ -90,12 +90,13 @@ def test_lam256_full_pair_vs_oracle(L, c2_ref, dtype, tol):
 @pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-12)], ids=["c64", "c128"])
 @pytest.mark.parametrize("case", [
     dict(n0=1024, n1=32, n2=32, ntheta=6, phi=25.0, h=64, w=32),      # z transforms of 2048 points
+    dict(n0=512, n1=16, n2=16, ntheta=2, phi=30.0, h=768, w=16),      # z of 1024, more rows than threads
     dict(n0=16, n1=1024, n2=32, ntheta=5, phi=30.0, h=16, w=32),      # y transforms of 2048 points
     dict(n0=16, n1=32, n2=1024, ntheta=3, phi=30.0, h=16, w=64),      # x transforms of 2048 points
     dict(n0=16, n1=512, n2=512, ntheta=3, phi=20.0, h=16, w=512),     # y, x of 1024; 2D DFT rows of 512
     dict(n0=32, n1=32, n2=32, ntheta=2, phi=20.0, h=1024, w=1024),    # 2D DFT of 1024^2
     dict(n0=32, n1=32, n2=32, ntheta=3, phi=35.0, h=512, w=512),      # 2D DFT of 512^2
-], ids=["z2048", "y2048", "x2048", "yx1024", "dft1024", "dft512"])
+], ids=["z2048", "zrows768", "y2048", "x2048", "yx1024", "dft1024", "dft512"])
 def test_compile_time_sizes_vs_oracle(L, dtype, tol, case):
     c = dict(case)
     phi = math.radians(c["phi"])
