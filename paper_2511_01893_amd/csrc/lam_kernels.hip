@@ -161,16 +161,16 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
   fft_cols<T, LN, LB>(buf, lM0, log2TX, tb, nth);
   const GaussW gw{D.beta};
   if constexpr (LN > 0) {
-    // one thread per detector row: its 2m weights once, then the TX columns of each stencil row as
-    // 16-byte chunks.  With at most one row per thread the rows go back through LDS (over the grid,
-    // after a barrier) so that the stores below are coalesced; otherwise straight from registers.
-    using C = Chunk16<T>;
-    constexpr int NCH = (1 << LB) / C::CW, NTH = ct_threads<T, LN, LB>();
-    static_assert(NCH >= 1 && ((1 << LB) % C::CW) == 0, "whole chunks per block row");
-    const int s = chunk_skew<NCH>();
-    const bool staged = D.h <= NTH;
-    for (int av0 = 0; av0 < D.h; av0 += NTH) {
-      const int av = av0 + tid;
+    if (D.h <= nth) {
+      // one thread per detector row: its 2m weights once, then the TX columns of each stencil row
+      // as 16-byte chunks; the rows go back through LDS (over the grid, after a barrier) so that the
+      // stores are coalesced.  (With more rows than threads the loop below is faster: each thread's
+      // rows would have to be stored straight from registers, one 16-byte piece per plane.)
+      using C = Chunk16<T>;
+      constexpr int NCH = (1 << LB) / C::CW;
+      static_assert(NCH >= 1 && ((1 << LB) % C::CW) == 0, "whole chunks per block row");
+      const int s = chunk_skew<NCH>();
+      const int av = tid;
       C acc[NCH];
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
@@ -187,39 +187,33 @@ __global__ __launch_bounds__(1024) void k_zfwd(const void* __restrict__ uin, cpx
           for (int c = 0; c < NCH; ++c) fma_chunk(acc[c], w, row[(c + s) & (NCH - 1)]);
         }
       }
-      if (staged) {
-        __syncthreads();
-        if (av < D.h) {
-          C* dst = reinterpret_cast<C*>(buf + av * (1 << LB));
-#pragma unroll
-          for (int c = 0; c < NCH; ++c) dst[(c + s) & (NCH - 1)] = acc[c];
-        }
-        __syncthreads();
-        for (int e = tid; e < D.h * TX; e += nth) {
-          const int a = e >> LB, b = e & (TX - 1);
-          u1[(size_t)a * plane + (size_t)y * D.n2 + x0 + b] = buf[e];
-        }
-      } else if (av < D.h) {
-        C* dst = reinterpret_cast<C*>(u1 + (size_t)av * plane + (size_t)y * D.n2 + x0);
+      __syncthreads();
+      if (av < D.h) {
+        C* dst = reinterpret_cast<C*>(buf + av * (1 << LB));
 #pragma unroll
         for (int c = 0; c < NCH; ++c) dst[(c + s) & (NCH - 1)] = acc[c];
       }
-    }
-  } else {
-    for (int e = tid; e < D.h * TX; e += nth) {
-      const int av = e >> log2TX, b = e & (TX - 1);
-      const int base = zb[av] - MH + 1;
-      const T dl = zd[av];
-      T ax = 0, ay = 0;
-#pragma unroll
-      for (int i = 0; i < 2 * MH; ++i) {
-        const T w = gw(dl - (T)(i + 1 - MH), T());
-        const cpx<T> g = buf[wrap1<P2>(base + i, M0) * TX + b];
-        ax += w * g.x;
-        ay += w * g.y;
+      __syncthreads();
+      for (int e = tid; e < D.h * TX; e += nth) {
+        const int a = e >> LB, b = e & (TX - 1);
+        u1[(size_t)a * plane + (size_t)y * D.n2 + x0 + b] = buf[e];
       }
-      u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b] = mk(ax, ay);
+      return;
     }
+  }
+  for (int e = tid; e < D.h * TX; e += nth) {
+    const int av = e >> log2TX, b = e & (TX - 1);
+    const int base = zb[av] - MH + 1;
+    const T dl = zd[av];
+    T ax = 0, ay = 0;
+#pragma unroll
+    for (int i = 0; i < 2 * MH; ++i) {
+      const T w = gw(dl - (T)(i + 1 - MH), T());
+      const cpx<T> g = buf[wrap1<P2>(base + i, M0) * TX + b];
+      ax += w * g.x;
+      ay += w * g.y;
+    }
+    u1[(size_t)av * plane + (size_t)y * D.n2 + x0 + b] = mk(ax, ay);
   }
 }
 
