@@ -4,7 +4,8 @@
 // Stage map (forward; the adjoint runs the transposed stages in reverse):
 //   k_zfwd      F_u1D: per (y, x-tile) column block: deconvolve by c_z, zero-pad
 //               n0 -> M0 = R n0, FFT along z in LDS, gather the h targets
-//               xi_z = n0 (k_v/h) cos(phi) with 2m table weights.
+//               xi_z = n0 (k_v/h) cos(phi) with 2m Gaussian weights evaluated
+//               from each row's tabulated base and offset.
 //   k_ycol_fwd  F_u2D part 1: per k_v slice and x-tile: deconvolve by c_y c_x,
 //               zero-pad n1 -> M1, FFT along y.
 //   k_xrow_fwd  F_u2D part 2: zero-pad rows n2 -> M2, FFT along x: the
