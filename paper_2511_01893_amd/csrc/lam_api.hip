@@ -228,12 +228,13 @@ int build(lam_plan_s* P) {
     P->rc[i] = std::exp(-P->beta * (2.0 * o + 1.0));
   }
   // slab: k_v slices per pass of the 2D step; automatic: the largest power of two whose grids (T and G)
-  // take at most 1 GiB (64 slices at 512^3: launches of a few thousand work-groups each)
+  // take at most 2 GiB (128 slices at 512^3 complex64, 16 at 1536^3: launches of ten to thirty thousand
+  // work-groups, whose tails cost ~1 % of the pair against 1 GiB slabs)
   const size_t per_slice = ((size_t)P->M1 * p.n2 + (size_t)P->M1 * P->M2) * P->csize;
   int S = p.slab;
   if (S <= 0) {
     S = 1;
-    while (S * 2 <= p.h && per_slice * S * 2 <= ((size_t)1 << 30)) S *= 2;
+    while (S * 2 <= p.h && per_slice * S * 2 <= ((size_t)2 << 30)) S *= 2;
   }
   if (S > p.h) S = p.h;
   P->slab = S;
