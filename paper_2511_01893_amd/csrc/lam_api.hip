@@ -55,6 +55,7 @@ struct lam_plan_s {
   unsigned long long uid = 0;  // unique per plan (lam_init), names the owner of a device's scratch
   std::vector<double> theta;
   int M0 = 0, M1 = 0, M2 = 0, Ntw = 0, Ntw3 = 0, slab = 0;
+  bool sblk = false;           // the workspace holds the spread's per-target block bytes
   double beta = 0;
   size_t csize = 8, rsize = 4;
   // host tables (FP64)
@@ -67,7 +68,7 @@ struct lam_plan_s {
   ListHost lh;
   // workspace layout (byte offsets)
   size_t off_tw = 0, off_tw3 = 0, off_cz = 0, off_cy = 0, off_cx = 0, off_zbase = 0, off_zdelta = 0, off_cth = 0, off_sth = 0,
-         off_rc = 0, off_line = 0, off_zrun = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
+         off_rc = 0, off_line = 0, off_zrun = 0, off_tlist = 0, off_toff = 0, off_gperm = 0, off_sperm = 0, off_sblk = 0, off_u1 = 0, off_p = 0, off_t = 0, off_g = 0, ws_need = 0;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   int ntx = 1, nty = 1;        // tiles of the oversampled grid per slice
@@ -263,6 +264,10 @@ int build(lam_plan_s* P) {
   P->off_toff = take((size_t)p.h * ((size_t)P->ntx * P->nty * 9 + 1) * sizeof(int));
   P->off_gperm = take((size_t)p.h * P->ntx * P->nty * sizeof(int));
   P->off_sperm = take((size_t)p.h * P->ntx * P->nty * sizeof(int));
+  // the complex64 fixed-point spread (64 x 64 tiles on grids of at least 128 x 128, m <= 4) reads one
+  // byte per target: its stencil base's 8 x 8 block within its own tile
+  P->sblk = p.dtype == LAM_C64 && TS == 64 && P->M1 >= 128 && P->M2 >= 128 && m <= 4;
+  P->off_sblk = P->sblk ? take((size_t)p.h * p.ntheta * p.w) : 0;
   P->off_u1 = take((size_t)p.h * p.n1 * p.n2 * P->csize);
   P->off_p = take((size_t)p.ntheta * p.h * p.w * P->csize);
   P->off_t = take((size_t)S * P->M1 * p.n2 * P->csize);
@@ -378,6 +383,7 @@ Tables<T> tables(const lam_plan_s* P, const unsigned char* w) {
   t.toff = reinterpret_cast<const int*>(w + P->off_toff);
   t.gperm = reinterpret_cast<const int*>(w + P->off_gperm);
   t.sperm = reinterpret_cast<const int*>(w + P->off_sperm);
+  t.sblk = P->sblk ? w + P->off_sblk : nullptr;
   t.zrun = reinterpret_cast<const unsigned*>(w + P->off_zrun);
   return t;
 }
@@ -514,6 +520,13 @@ int build_lists(lam_plan_s* P, unsigned char* ws, ListHost& lh) {
   if (nbad)
     return fail(LAM_ERR_STATE, "target lists: " + std::to_string(nbad) +
                                    " entries out of range, misfiled or listed twice");
+  if (P->sblk)
+    for (int k0 = 0; k0 < h; k0 += chunk) {
+      const int rc = hip_status(launch_list_blocks<T>(P->cfg, k0, std::min(chunk, h - k0), P->D, tb,
+                                                      ws + P->off_sblk, nullptr),
+                                "target blocks");
+      if (rc) return rc;
+    }
   return hip_status(hipDeviceSynchronize(), "target list build");
 }
 

@@ -108,6 +108,25 @@ __global__ __launch_bounds__(256) void k_list_fill(Dims D, Tables<T> tb, int log
   });
 }
 
+// sblk[k][i] for the lists of slices [k0, k0 + gridDim.y), one block per (tile, slice): the 8 x 8 block
+// (8 by + bx) of each listed target's stencil base within its own tile (the same FP64 coordinates as the
+// kernels), so that the complex64 spread's first pass places a sample without evaluating them.
+template <typename T, int MH>
+__global__ __launch_bounds__(256) void k_list_blocks(Dims D, Tables<T> tb, int log2TS, int k0,
+                                                     unsigned char* __restrict__ sblk) {
+  const int ntx = D.M2 >> log2TS, nty = D.M1 >> log2TS;
+  const int tile = blockIdx.x, k = k0 + blockIdx.y, tx = tile % ntx, ty = tile / ntx;
+  const int* of = tb.toff + (size_t)k * ((size_t)ntx * nty * 9 + 1) + (size_t)tile * 9;
+  const size_t base = (size_t)k * D.ntheta * D.w;
+  for (int i = of[0] + (int)threadIdx.x; i < of[9]; i += blockDim.x) {
+    const int id = tb.tlist[base + i], t = id >> 12, aku = id & 4095;
+    double sx, sy;
+    target_coords(D.xy, tb.cth[t], tb.sth[t], k, aku, sx, sy);
+    const int oy = pmod((int)floor(sy) - (ty << log2TS), D.M1), ox = pmod((int)floor(sx) - (tx << log2TS), D.M2);
+    sblk[base + i] = (unsigned char)(((oy >> 3) << 3) | (ox >> 3));
+  }
+}
+
 // Exact check of the lists of slices [k0, k0 + gridDim.y), one block per (tile, slice): every entry
 // must name a target in range, classify (by the same FP64 coordinates) into the tile and border
 // class whose list holds it, and appear only once in its slice (a bit per target in `seen`, cleared
@@ -645,16 +664,21 @@ __global__ __launch_bounds__(512) void k_scatter_fx(const cpx<float>* __restrict
   const unsigned hw = (unsigned)D.h * D.w;   // < 2^24
   const int kw = k * D.w;
   __syncthreads();
-  // pass 1: block sums of max(|re|, |im|) at the stencil bases
+  // pass 1: block sums of max(|re|, |im|) at the stencil bases.  A target's block in this tile is its
+  // block in its own tile (the plan's byte), or for a neighbour's border class the facing edge block:
+  // slots 1-3 / 4-6 the left / right neighbour (bx 0 / 7), 7 / 8 the upper / lower one (by 0 / 7),
+  // 9-12 the corners.
+  const unsigned char* SB = tb.sblk + (size_t)k * D.ntheta * D.w;
   for (int i = tid; i < total; i += nth) {
-    const int pe = L[idx_of(i)];
-    const unsigned t = (unsigned)pe >> 12;
-    const int uk = pe & 4095;
-    const cpx<float> v = in[(size_t)t * hw + (unsigned)(kw + uk)];
-    double sx, sy;
-    target_coords(D.xy, tb.cth[t], tb.sth[t], k, uk, sx, sy);
-    const int bx = min(max(fold_rel<P2>((int)floor(sx) - x0, M2) >> 3, 0), 7);
-    const int by = min(max(fold_rel<P2>((int)floor(sy) - y0, M1) >> 3, 0), 7);
+    int q = 0, idx = rb[0] + i;
+#pragma unroll
+    for (int s = 1; s < kSpreadSlots; ++s)
+      if (i >= pre[s]) { q = s; idx = rb[s] + (i - pre[s]); }
+    const int pe = L[idx];
+    const unsigned b = SB[idx];
+    const cpx<float> v = in[(size_t)((unsigned)pe >> 12) * hw + (unsigned)(kw + (pe & 4095))];
+    const int bx = (q == 0 || q == 7 || q == 8) ? (int)(b & 7u) : ((q >= 4 && q <= 6) || q == 10 || q == 12 ? 7 : 0);
+    const int by = q <= 6 ? (int)(b >> 3) : (q == 8 || q == 11 || q == 12 ? 7 : 0);
     atomicAdd(blk + by * 8 + bx, (double)fmaxf(fabsf(v.x), fabsf(v.y)));
   }
   __syncthreads();
@@ -799,6 +823,16 @@ hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, c
 }
 
 template <typename T>
+hipError_t launch_list_blocks(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb,
+                              unsigned char* sblk, hipStream_t s) {
+  const int ntx = D.M2 >> c.g_log2TS, nty = D.M1 >> c.g_log2TS;
+  LAM_MH_SWITCH(D.m, {
+    hipLaunchKernelGGL((k_list_blocks<T, MH>), dim3(ntx * nty, ns), dim3(256), 0, s, D, tb, c.g_log2TS, k0, sblk);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_list_check(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, unsigned* seen,
                              int* bad, hipStream_t s) {
   const int ntx = D.M2 >> c.g_log2TS, nty = D.M1 >> c.g_log2TS;
@@ -851,6 +885,8 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
                                            hipStream_t);                                                         \
   template hipError_t launch_list_fill<T>(const LaunchCfg&, int, int, const Dims&, const Tables<T>&, const int*,  \
                                           int*, hipStream_t);                                                    \
+  template hipError_t launch_list_blocks<T>(const LaunchCfg&, int, int, const Dims&, const Tables<T>&,          \
+                                           unsigned char*, hipStream_t);                                         \
   template hipError_t launch_list_check<T>(const LaunchCfg&, int, int, const Dims&, const Tables<T>&, unsigned*, \
                                           int*, hipStream_t);                                                    \
   template hipError_t launch_gather<T>(const LaunchCfg&, const cpx<T>*, cpx<T>*, const cpx<T>*, int, int,        \

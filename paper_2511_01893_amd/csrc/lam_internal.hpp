@@ -65,6 +65,8 @@ struct Tables {
   const int* toff;    // per slice [n_tiles 9 + 1]: offsets of the (tile, class) lists within the slice
   const int* gperm;   // per slice [n_tiles]: tiles in decreasing order of gather work
   const int* sperm;   // per slice [n_tiles]: tiles in decreasing order of spread work
+  const unsigned char* sblk;   // aligned with tlist: the 8 x 8 block (8 by + bx) of each target's stencil
+                               // base within its own tile (complex64 fixed-point spread only; else null)
 };
 
 // The list ranges [b, e) of one slice that tile (ty, tx) consumes in the adjoint
@@ -144,6 +146,9 @@ hipError_t launch_list_count(const LaunchCfg& c, int k0, int ns, const Dims& D, 
 template <typename T>
 hipError_t launch_list_fill(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, const int* offs,
                             int* lists, hipStream_t s);
+template <typename T>
+hipError_t launch_list_blocks(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb,
+                              unsigned char* sblk, hipStream_t s);
 template <typename T>
 hipError_t launch_list_check(const LaunchCfg& c, int k0, int ns, const Dims& D, const Tables<T>& tb, unsigned* seen,
                              int* bad, hipStream_t s);
