@@ -623,7 +623,7 @@ def offload_evaluate(plan, phase_s, sizes, access, link_bps):
             L = start[k] + access[v][k][1]
             F = start[kn] + access[v][kn][0] + shift
             S = start[kn] + shift
-            out.append((L, F, S, bool(access[v][kn][2])))
+            out.append((L, F, S, start[kn], bool(access[v][kn][2])))
         return out
 
     def first_fit(busy, ready, dur):
@@ -639,8 +639,10 @@ def offload_evaluate(plan, phase_s, sizes, access, link_bps):
     def evaluate(plan):
         gaps = [(g, v) for v in plan for g in gaps_of(v)]
         absent, live = [], []
-        for (L, F, S, dead), v in gaps:
+        ends = {}                                               # a dead gap ends exactly where phase k' starts
+        for (L, F, S, S0, dead), v in gaps:
             if dead:
+                ends[len(absent)] = S0
                 absent.append((v, L, S))
             else:
                 live.append((L, F, S, v))
@@ -665,11 +667,11 @@ def offload_evaluate(plan, phase_s, sizes, access, link_bps):
             delay += max(0.0, b + dur - F)
             absent.append((v, oe, b))
         ev = []
-        for v, a, z in absent:                                  # absences folded onto [0, Ttot)
+        for j, (v, a, z) in enumerate(absent):                  # absences folded onto [0, Ttot)
             if z - a >= Ttot:
                 ev += [(0.0, -sizes[v]), (Ttot, sizes[v])]
                 continue
-            a0, z0 = a % Ttot, z % Ttot
+            a0, z0 = a % Ttot, ends.get(j, z % Ttot)
             if z0 >= a0:
                 ev += [(a0, -sizes[v]), (z0, sizes[v])]
             else:

@@ -13,7 +13,8 @@
 // from the offload's end to the prefetch's start, and a prefetch ending after F delays the
 // iteration by the difference (T sums the delays).  Offloads take the link in the order of their
 // gaps' last accesses, then prefetches in the order of their planned starts.  M is the total size
-// of the variables less the plan's peak of resident sizes over the iteration.
+// of the variables less the plan's peak of resident sizes over the iteration (a dead gap's absence
+// ends exactly at its phase's start when folded onto one iteration, not at a rounded start + period).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -33,6 +34,7 @@ struct Gap {
 struct Absence {
   int v;
   double a, z;
+  double z0;   // >= 0: the end folded onto [0, Ttot) exactly (a dead gap ends where its phase starts)
 };
 
 struct Plan {
@@ -54,7 +56,7 @@ Plan evaluate(const std::vector<int>& plan, const double* start, int P, const la
       const double L = start[k] + vars[v].last[k];
       const double F = start[kn] + vars[v].first[kn] + shift;
       const double S = start[kn] + shift;
-      if (vars[v].writes_first[kn]) absent.push_back({v, L, S});
+      if (vars[v].writes_first[kn]) absent.push_back({v, L, S, start[kn]});
       else live.push_back({L, F, S, false, v});
     }
   }
@@ -86,7 +88,7 @@ Plan evaluate(const std::vector<int>& plan, const double* start, int P, const la
     busy.push_back({t, t + dur});
     std::sort(busy.begin(), busy.end(), by_start);
     r.T += std::max(0.0, t + dur - k.F);
-    absent.push_back({k.v, k.oe, t});
+    absent.push_back({k.v, k.oe, t, -1.0});
   }
   // peak of the resident sizes over one iteration (absences folded onto [0, Ttot))
   struct Ev { double t, d; };
@@ -98,7 +100,7 @@ Plan evaluate(const std::vector<int>& plan, const double* start, int P, const la
       ev.push_back({Ttot, s});
       continue;
     }
-    const double a0 = std::fmod(a.a, Ttot), z0 = std::fmod(a.z, Ttot);
+    const double a0 = std::fmod(a.a, Ttot), z0 = a.z0 >= 0.0 ? a.z0 : std::fmod(a.z, Ttot);
     if (z0 >= a0) {
       ev.push_back({a0, -s});
       ev.push_back({z0, s});

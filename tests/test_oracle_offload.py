@@ -117,3 +117,26 @@ def test_library_planner_argument_errors():
         L.offload_plan([1.0], _lib_vars({"A": 1.0}, {"A": {0: (0.6, 0.5, False)}}), 0.0, 1e9)
     with pytest.raises(L.LamError):
         L.offload_plan([1.0], v, 0.0, 0.0)
+
+
+def test_dead_gaps_abutting_at_a_phase_boundary():
+    """G written and used in phase 0 only, D written in phase 1 and read in phase 2: both gaps are
+    dead, G is absent through phases 1-2 and D through phase 0, so they are never present together
+    and M is one size with no transfer, whatever the phase durations.  D's absence ends where phase
+    1 starts, the instant G's begins: a folded end computed as (start + period) mod period can land
+    an ulp early and count both as present (it did for phases of 75.77, 3.59 and 0.67 ms)."""
+    rng = random.Random(5)
+    cases = [[0.07577, 0.00359, 0.00067], [0.07637, 0.00352, 0.00066]]
+    cases += [[rng.uniform(1e-4, 0.2) for _ in range(3)] for _ in range(300)]
+    for ph in cases:
+        a = {"G": {0: (0.0, ph[0], True)}, "D": {1: (0.0, ph[1], True), 2: (0.0, ph[2], False)}}
+        M, T, _ = O.offload_evaluate(["G", "D"], ph, {"G": 5.0, "D": 5.0}, a, 1e9)
+        assert M == 5.0 and T == 0.0, ph
+
+
+def test_library_dead_gaps_abutting_at_a_phase_boundary():
+    from paper_2511_01893_amd import lam as L
+    for ph in ([0.07577, 0.00359, 0.00067], [0.07637, 0.00352, 0.00066]):
+        a = {"G": {0: (0.0, ph[0], True)}, "D": {1: (0.0, ph[1], True), 2: (0.0, ph[2], False)}}
+        r = L.offload_evaluate(ph, _lib_vars({"G": 5.0, "D": 5.0}, a), 0.0, 1e9, ["G", "D"])
+        assert r["M"] == 5.0 and r["T"] == 0.0, ph
