@@ -864,7 +864,7 @@ hipError_t launch_scatter(const LaunchCfg& c, const cpx<T>* in, cpx<T>* Gb, int 
   const bool p2 = pow2_grid(D);
   LAM_MH_SWITCH(D.m, {
     if constexpr (std::is_same<T, float>::value && MH <= 4) {
-      if (fast_tiles(c, D)) {   // complex64: fixed-point accumulation
+      if (fast_tiles(c, D) && tb.sblk) {   // complex64: fixed-point accumulation (needs the plan's block bytes)
         auto kf = p2 ? k_scatter_fx<MH, true> : k_scatter_fx<MH, false>;
         if ((e = prep(kf, fx_lds<MH>())) != hipSuccess) return e;
         hipLaunchKernelGGL(kf, dim3(ntiles * ns), dim3(512), fx_lds<MH>(), s, in, Gb, k0, D, tb);
